@@ -1,0 +1,206 @@
+"""Benchmark: DA-CSR (int16 offsets) vs CSR (int32 columns) SpMV on one MI355X.
+
+One step = one DA-CSR SpMV y = A x (float64, beta = 0) on the 3D 27-point
+stencil over a 128^3 grid in natural order (n 2,097,152, nnz 55,742,968,
+bandwidth 16513).  `value` is the effective bandwidth of that step under the
+traffic model of Eq. 3 plus x and y (Sec. 4):
+    T = 4 (n+1) + nnz (2 + 8) + 8 n (x) + 8 n (y)
+divided by the measured time per step.  The CSR comparison, the streaming
+ceiling and the CPU oracle baseline are measured in the same run, outside the
+timed steps, and reported beside it.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def model_bytes(nrows, ncols, nnz, iindex, scalar=8, nrhs=1, beta_nonzero=False):
+    # Eq. 3 with int32 row pointers, plus x read once and y written (and read)
+    return (4 * (nrows + 1) + nnz * (iindex + scalar) + scalar * nrhs * ncols
+            + scalar * nrhs * nrows * (2 if beta_nonzero else 1))
+
+
+def time_launches(fn, reps):
+    """Mean seconds per call of fn() over reps back-to-back calls (HIP events
+    on torch's current stream, which is the stream the library launches on)."""
+    import torch
+
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(reps):
+        fn()
+    stop.record()
+    stop.synchronize()
+    return start.elapsed_time(stop) * 1e-3 / reps
+
+
+def epochs(fn, reps, n_epochs=5):
+    """Minimum over epochs of the mean time per call (the paper's nanobench
+    protocol takes the minimum over epochs)."""
+    return min(time_launches(fn, reps) for _ in range(n_epochs))
+
+
+def cpu_baseline(A, e, x, budget_s=12.0):
+    """The CPU oracle's DA-CSR SpMV on the same matrix, repeated until about
+    budget_s seconds have passed (NumPy, one thread)."""
+    from oracle.spmv import spmv_da
+
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        spmv_da(A.nrows, A.ncols, e["rowptr"], e["off"], e["vals"], x)
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    return dt, reps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--tune-reps", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2307_06305_amd as D
+    from paper_2307_06305_amd.tuning import autotune, candidates, config_name
+    from workloads import config_description, config_matrix, config_vector
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    props = torch.cuda.get_device_properties(dev)
+    log(f"device {props.name}, {props.multi_processor_count} CUs")
+
+    t = time.time()
+    A = config_matrix(1)
+    log(f"matrix {A.name}: n={A.nrows} nnz={A.nnz} ({time.time() - t:.1f}s)")
+    t = time.time()
+    e = D.encode(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, allow_rcm=True)
+    log(f"encode: w={e['w']} permuted={e['permuted']} ({time.time() - t:.1f}s)")
+    M = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], e["vals"])
+    Cm = D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals)
+    x = config_vector(1, A.ncols)
+    xd = torch.from_numpy(x).to(dev)
+    yd = torch.zeros(A.nrows, dtype=torch.float64, device=dev)
+    yc = torch.zeros_like(yd)
+
+    # streaming ceiling: a plain 16-byte-load read of 2 GiB
+    buf = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
+    sink = torch.zeros(65536, dtype=torch.float64, device=dev)
+    t_read = epochs(lambda: D.stream_read(buf, sink), 10, 3)
+    stream_gbs = buf.numel() / t_read / 1e9
+    del buf
+    log(f"streaming read ceiling: {stream_gbs:.0f} GB/s")
+
+    # pick launch shapes (autotuner)
+    best_da, times_da = autotune(M, xd, yd, reps=args.tune_reps)
+    best_csr, times_csr = autotune(Cm, xd, yc, reps=args.tune_reps)
+    log(f"DA best {config_name(best_da)} {times_da[best_da]*1e6:.1f}us; "
+        f"CSR best {config_name(best_csr)} {times_csr[best_csr]*1e6:.1f}us")
+
+    T_da = model_bytes(A.nrows, A.ncols, A.nnz, 2)
+    T_csr = model_bytes(A.nrows, A.ncols, A.nnz, 4)
+
+    # timed region: K DA-CSR SpMVs
+    for _ in range(args.warmup):
+        M.spmv(xd, yd)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    start.record()
+    for _ in range(args.steps):
+        M.spmv(xd, yd)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    t_da_events = start.elapsed_time(stop) * 1e-3 / args.steps
+    ms_per_step = wall * 1e3 / args.steps
+
+    # comparison path and repeat measurement (min over epochs)
+    t_da = epochs(lambda: M.spmv(xd, yd), 50)
+    t_csr = epochs(lambda: Cm.csr_spmv(xd, yc), 50)
+
+    # correctness of the timed output against CSR on the same x
+    torch.cuda.synchronize()
+    diff = (yd - yc).abs().max().item()
+
+    W = 2 * A.nnz + 2 * A.nrows
+    da_gbs = T_da / t_da_events / 1e9
+    res = {
+        "metric": "DA-CSR vs CSR SpMV effective GB/s, % HBM peak, speedup; CG time to 1e-10",
+        "value": round(T_da / (ms_per_step * 1e-3) / 1e9, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": config_description(1), "n": A.nrows, "nnz": A.nnz,
+                   "bandwidth": e["w"], "index": "int16 DA offsets", "values": "f64",
+                   "launch": config_name(best_da)},
+        "roofline": {"bound": "hbm", "achieved": round(da_gbs, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(da_gbs / HBM_PEAK_GBS, 4), "traffic": None},
+        "da": {"us": round(t_da * 1e6, 2), "model_bytes": T_da,
+               "gbs": round(T_da / t_da / 1e9, 1),
+               "pct_hbm_peak": round(100 * T_da / t_da / 1e9 / HBM_PEAK_GBS, 2),
+               "gflops": round(W / t_da / 1e9, 1), "launch": config_name(best_da)},
+        "csr": {"us": round(t_csr * 1e6, 2), "model_bytes": T_csr,
+                "gbs": round(T_csr / t_csr / 1e9, 1),
+                "pct_hbm_peak": round(100 * T_csr / t_csr / 1e9 / HBM_PEAK_GBS, 2),
+                "gflops": round(W / t_csr / 1e9, 1), "launch": config_name(best_csr)},
+        "speedup": round(t_csr / t_da, 4),
+        "predicted_speedup": round(T_csr / T_da, 4),
+        "uplift_fraction": round((t_csr / t_da - 1) / (T_csr / T_da - 1), 3),
+        "stream_read_gbs": round(stream_gbs, 1),
+        "max_abs_diff_da_vs_csr": diff,
+        "paper_cpu_context": {"uplift_st": 0.11, "uplift_mt": 0.175, "predicted": 0.20},
+    }
+
+    if not args.no_cpu:
+        t_cpu, reps = cpu_baseline(A, e, x)
+        res["cpu_baseline"] = {
+            "value": round(T_da / t_cpu / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle DA-CSR SpMV (NumPy, float64) on the full workload, {reps} runs, "
+                      f"{t_cpu:.2f} s each",
+        }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

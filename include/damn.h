@@ -1,0 +1,213 @@
+/*
+ * damn.h -- diagonally-addressed (DA) CSR sparse matrix-vector products on
+ * AMD Instinct MI355X (gfx950).  C ABI of libdamn.so.
+ *
+ * Storage (paper Sec. 2, Listing 1): a matrix A of nrows x ncols is held as
+ *   rowptr[nrows+1]  int32, rowptr[0] = 0, non-decreasing, rowptr[nrows] = nnz
+ *   colids[nnz]      CSR: the column c_i in [0, ncols)           (int32)
+ *                    DA-CSR: the offset c_i - r_i in [-w, w]     (int16)
+ *   values[nnz]      float64 or float32
+ * where w is the bandwidth of Eq. 2, max |c - r| over stored entries.  A
+ * matrix fits 16-bit DA-CSR when w < 2^15 (Sec. 2, Example 2).  Explicitly
+ * stored zeros are entries (footnote of Example 2); empty rows, repeated
+ * columns and unsorted rows are allowed.
+ *
+ * Product (Sec. 4): y <- alpha*A*x + beta*y.  beta == 0 never reads y, and
+ * alpha == 0 never reads A or x (BLAS convention; the paper's listing always
+ * reads y).
+ *
+ * Conventions for every call:
+ * - Sizes are int32 (the paper selects matrices whose CSR fits 32-bit
+ *   signed indices, Sec. 3).
+ * - Host pointers are read during the call and never retained.  Device
+ *   pointers (x, y, X, Y, b) belong to the caller and must stay valid until
+ *   the work queued on `stream` has finished.
+ * - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *   Device calls only queue work on it and return without synchronising,
+ *   unless stated otherwise.
+ * - Every call returns a damn_status.  On any error the outputs are left
+ *   untouched and nothing is queued.
+ */
+#ifndef DAMN_H
+#define DAMN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DAMN_OK = 0,
+  DAMN_ERR_INVALID_ARG = -1,   /* null pointer, negative size, bad enum     */
+  DAMN_ERR_BAD_CSR = -2,       /* rowptr/colids do not form a valid matrix  */
+  DAMN_ERR_NO_FIT = -3,        /* bandwidth >= 2^15, also after reordering  */
+  DAMN_ERR_HIP = -4,           /* a HIP runtime call failed                 */
+  DAMN_ERR_ALLOC = -5,         /* host or device allocation failed          */
+  DAMN_ERR_UNSUPPORTED = -6,   /* combination not provided (e.g. nrhs > 8)  */
+  DAMN_ERR_NOT_CONVERGED = -7, /* iteration limit reached                   */
+  DAMN_ERR_BREAKDOWN = -8      /* p.Ap <= 0: matrix not positive definite   */
+} damn_status;
+
+typedef enum { DAMN_F64 = 0, DAMN_F32 = 1 } damn_dtype;
+
+/* Column-index kind of a device matrix. */
+typedef enum { DAMN_FORMAT_DA16 = 0, DAMN_FORMAT_CSR32 = 1 } damn_format;
+
+/* Opaque device matrix; owns its device arrays. */
+typedef struct damn_mat_s* damn_mat;
+
+/* Human-readable text for a status code (static storage). */
+const char* damn_status_string(int status);
+/* Library version string (static storage). */
+const char* damn_version(void);
+
+/* ------------------------------------------------------------------------
+ * Host-only preprocessing (no GPU use).
+ * --------------------------------------------------------------------- */
+
+/* Bandwidth check (Eq. 2; 16-bit rule of Sec. 2, Example 2 and Sec. 3).
+ * In:  int32 CSR (rowptr[nrows+1], colids[rowptr[nrows]]), host memory.
+ * Out: *w = max |c - r|, *lo = max(r - c, 0), *hi = max(c - r, 0) over all
+ *      stored entries (0 for an empty matrix); *fits = (w < 32768).
+ * Errors: DAMN_ERR_INVALID_ARG (null pointer with nnz > 0, negative size),
+ *         DAMN_ERR_BAD_CSR (rowptr not starting at 0 / decreasing / not
+ *         ending at nnz, or a column outside [0, ncols)). */
+int damn_fit_check(int32_t nrows, int32_t ncols, const int32_t* rowptr,
+                   const int32_t* colids, int32_t* w, int32_t* lo, int32_t* hi,
+                   int32_t* fits);
+
+/* Reverse Cuthill-McKee ordering (cited in Sec. 2, Example 2, and Sec. 3;
+ * details fixed here): graph = pattern of A + A^T without self loops;
+ * adjacency ordered by (degree, index); components seeded by the unvisited
+ * vertex of smallest (degree, index) and started from a George-Liu
+ * pseudo-peripheral vertex; breadth-first Cuthill-McKee; the concatenated
+ * order reversed.
+ * In:  square int32 CSR of order n (host).
+ * Out: perm[n], new position -> old index (host, caller-allocated).
+ * Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_BAD_CSR, DAMN_ERR_ALLOC. */
+int damn_rcm(int32_t n, const int32_t* rowptr, const int32_t* colids,
+             int32_t* perm);
+
+/* CSR -> DA-CSR with 16-bit offsets (Sec. 2, Example 1).
+ * If w < 32768 in the given order: rowptr and values are copied, and
+ * off[i] = colids[i] - r_i, entry order unchanged; perm_out (if not NULL)
+ * gets the identity and *permuted = 0.
+ * Otherwise, if allow_rcm != 0 and the matrix is square: the RCM
+ * permutation is applied as P A P^T (new row i = old row perm[i], column c
+ * relabelled to inv[c]; within a row entries ordered by new column, equal
+ * columns keep their old order), the fit is checked again and *permuted = 1.
+ * Products with a permuted matrix are in permuted space: x_p[i] = x[perm[i]]
+ * and y[perm[i]] = y_p[i].
+ * In:  host int32 CSR with float64 values.
+ * Out: rowptr_out[nrows+1], off_out[nnz], vals_out[nnz] (float64),
+ *      perm_out[nrows] (may be NULL), *permuted, *w_out (bandwidth of the
+ *      result, or of the best form found when NO_FIT).  All host memory.
+ * Errors: DAMN_ERR_NO_FIT (only *w_out is written), DAMN_ERR_INVALID_ARG,
+ *         DAMN_ERR_BAD_CSR, DAMN_ERR_ALLOC. */
+int damn_encode(int32_t nrows, int32_t ncols, const int32_t* rowptr,
+                const int32_t* colids, const double* vals, int32_t allow_rcm,
+                int32_t* rowptr_out, int16_t* off_out, double* vals_out,
+                int32_t* perm_out, int32_t* permuted, int32_t* w_out);
+
+/* ------------------------------------------------------------------------
+ * Device matrices.
+ * --------------------------------------------------------------------- */
+
+/* Upload a DA-CSR matrix (int16 offsets) to the current device.
+ * In:  host rowptr[nrows+1], off[nnz], vals[nnz] of type vals_dtype; the
+ *      device copy stores values as store_dtype (float64 -> float32 rounds
+ *      to nearest even).  Every r + off[i] must lie in [0, ncols) (checked
+ *      on the host, so no kernel can read outside x; Sec. 4, remark on
+ *      non-square matrices).
+ * Out: *out, a handle owning its device memory (free with damn_destroy).
+ * The copies are ordered on `stream`; the call synchronises the stream
+ * before returning so the host arrays may be freed at once.
+ * Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_BAD_CSR, DAMN_ERR_ALLOC,
+ *         DAMN_ERR_HIP. */
+int damn_create(damn_mat* out, int32_t nrows, int32_t ncols,
+                const int32_t* rowptr, const int16_t* off, const void* vals,
+                int32_t vals_dtype, int32_t store_dtype, void* stream);
+
+/* Upload a plain int32 CSR matrix (the comparison format of Sec. 4).
+ * Same contract as damn_create with absolute columns colids[nnz]. */
+int damn_csr_create(damn_mat* out, int32_t nrows, int32_t ncols,
+                    const int32_t* rowptr, const int32_t* colids,
+                    const void* vals, int32_t vals_dtype, int32_t store_dtype,
+                    void* stream);
+
+/* Release a handle (waits for the device to finish using it). */
+int damn_destroy(damn_mat A);
+
+/* Shape and format of a handle (any out pointer may be NULL). */
+int damn_mat_info(damn_mat A, int32_t* nrows, int32_t* ncols, int64_t* nnz,
+                  int32_t* format, int32_t* dtype);
+
+/* ------------------------------------------------------------------------
+ * Products (Sec. 4, Listing 2).  x has ncols entries, y has nrows, both of
+ * the matrix's value dtype, in device memory.
+ * --------------------------------------------------------------------- */
+
+/* y <- alpha*A*x + beta*y for a DA-CSR handle: row r accumulates
+ * values[i] * x[r + off[i]] (the shifted-x access of Sec. 4).
+ * Errors: DAMN_ERR_INVALID_ARG (null, or a CSR handle), DAMN_ERR_HIP. */
+int damn_spmv(damn_mat A, const void* x, void* y, double alpha, double beta,
+              void* stream);
+
+/* Same product for a plain CSR handle (absolute columns). */
+int damn_csr_spmv(damn_mat A, const void* x, void* y, double alpha,
+                  double beta, void* stream);
+
+/* Y <- alpha*A*X + beta*Y for nrhs right-hand sides, 1 <= nrhs <= 8.
+ * X is ncols x nrhs and Y is nrows x nrhs, both row-major (the nrhs values
+ * of one row are adjacent).  Works on DA-CSR and CSR handles.
+ * Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_UNSUPPORTED (nrhs > 8). */
+int damn_spmm(damn_mat A, const void* X, void* Y, int32_t nrhs, double alpha,
+              double beta, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Kernel configuration.
+ * --------------------------------------------------------------------- */
+
+/* Kernel variants of the product:
+ *   DAMN_VAR_VECTOR: `lanes` lanes of a wavefront per row (1..64, power of
+ *                    two; 1 = one row per lane), `unroll` independent partial
+ *                    sums per lane (1, 2 or 4).
+ *   DAMN_VAR_STREAM: workgroups take tiles of whole rows holding at most
+ *                    `tile` entries, stream offsets and values with aligned
+ *                    16-byte loads through LDS, and reduce each row with
+ *                    `lanes` lanes (1..64).  `unroll` unused.
+ */
+typedef enum { DAMN_VAR_VECTOR = 0, DAMN_VAR_STREAM = 1 } damn_variant;
+
+typedef struct {
+  int32_t variant;
+  int32_t lanes;
+  int32_t unroll;
+  int32_t tile; /* stream variant only: entries per tile (256..8192) */
+} damn_config;
+
+/* Set / read the configuration used by damn_spmv, damn_csr_spmv and
+ * damn_spmm on this handle.  A new handle starts with a default derived
+ * from its mean row length.  Errors: DAMN_ERR_INVALID_ARG,
+ * DAMN_ERR_UNSUPPORTED, DAMN_ERR_ALLOC/HIP (stream tiles are built on first
+ * use of a tile size). */
+int damn_set_config(damn_mat A, const damn_config* cfg);
+int damn_get_config(damn_mat A, damn_config* cfg);
+
+/* ------------------------------------------------------------------------
+ * Measurement helpers.
+ * --------------------------------------------------------------------- */
+
+/* Streaming ceiling probe: reads `bytes` (multiple of 16) from device
+ * buffer src with 16-byte loads and writes one float64 per workgroup into
+ * sink[0 .. 65535] (device).  Used to measure the achievable HBM read rate
+ * and to calibrate traffic counters.  Errors: DAMN_ERR_INVALID_ARG. */
+int damn_stream_read(const void* src, size_t bytes, double* sink, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DAMN_H */

@@ -1,0 +1,260 @@
+"""Python binding of libdamn.so (diagonally-addressed CSR SpMV on MI355X).
+
+Argument marshalling only: every step runs in the C++/HIP library.  Host
+arrays are NumPy; device vectors are torch tensors on a HIP device, passed
+by pointer together with the current torch stream.  Importing the package
+loads the library and raises if it has not been built
+(`python -m paper_2307_06305_amd.build`).
+
+Names follow the C ABI of include/damn.h without the `damn_` prefix.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from ._lib import DamnError, NoFit, lib, LIB_PATH  # noqa: F401
+
+F64, F32 = 0, 1
+FORMAT_DA16, FORMAT_CSR32 = 0, 1
+VAR_VECTOR, VAR_STREAM = 0, 1
+
+_I32P = C.POINTER(C.c_int32)
+
+
+def _check(st, what):
+    if st != 0:
+        raise DamnError(st, what)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _csr_arrays(nrows, rowptr, *entry_arrays):
+    """The C ABI takes nnz from rowptr[nrows]: check the array lengths
+    against it before handing the pointers over."""
+    rp = _i32(rowptr)
+    if nrows < 0 or rp.shape != (nrows + 1,):
+        raise DamnError(-2, "rowptr must have nrows+1 entries")
+    nnz = int(rp[nrows])
+    for a in entry_arrays:
+        if nnz < 0 or len(a) != nnz:
+            raise DamnError(-2, "entry arrays must have rowptr[nrows] entries")
+    return rp
+
+
+def version() -> str:
+    return lib.damn_version().decode()
+
+
+def status_string(code: int) -> str:
+    return lib.damn_status_string(int(code)).decode()
+
+
+# ---------------------------------------------------------------------------
+# host preprocessing
+# ---------------------------------------------------------------------------
+
+def fit_check(nrows, ncols, rowptr, colids):
+    """(w, lo, hi, fits) of Eq. 2 for an int32 CSR matrix (host)."""
+    c = _i32(colids)
+    rp = _csr_arrays(nrows, rowptr, c)
+    w, lo, hi, f = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib.damn_fit_check(nrows, ncols, _ptr(rp, C.c_int32), _ptr(c, C.c_int32),
+                              C.byref(w), C.byref(lo), C.byref(hi), C.byref(f)), "fit_check")
+    return w.value, lo.value, hi.value, bool(f.value)
+
+
+def rcm(n, rowptr, colids):
+    """Reverse Cuthill-McKee permutation (new -> old), int32 (host)."""
+    c = _i32(colids)
+    rp = _csr_arrays(n, rowptr, c)
+    perm = np.empty(n, dtype=np.int32)
+    _check(lib.damn_rcm(n, _ptr(rp, C.c_int32), _ptr(c, C.c_int32), _ptr(perm, C.c_int32)),
+           "rcm")
+    return perm
+
+
+def encode(nrows, ncols, rowptr, colids, vals, allow_rcm=True):
+    """CSR -> DA-CSR int16 (host).  Returns dict(rowptr, off, vals, perm,
+    permuted, w); raises NoFit (with .w) when no fitting form exists."""
+    c = _i32(colids)
+    v = np.ascontiguousarray(vals, dtype=np.float64)
+    rp = _csr_arrays(nrows, rowptr, c, v)
+    nnz = int(rp[nrows])
+    rp_out = np.empty(nrows + 1, dtype=np.int32)
+    off = np.empty(nnz, dtype=np.int16)
+    v_out = np.empty(nnz, dtype=np.float64)
+    perm = np.empty(nrows, dtype=np.int32)
+    permuted, w = C.c_int32(), C.c_int32()
+    st = lib.damn_encode(nrows, ncols, _ptr(rp, C.c_int32), _ptr(c, C.c_int32),
+                         _ptr(v, C.c_double), int(allow_rcm), _ptr(rp_out, C.c_int32),
+                         _ptr(off, C.c_int16), _ptr(v_out, C.c_double), _ptr(perm, C.c_int32),
+                         C.byref(permuted), C.byref(w))
+    if st == -3:
+        raise NoFit(w.value)
+    _check(st, "encode")
+    return {"rowptr": rp_out, "off": off, "vals": v_out, "perm": perm,
+            "permuted": bool(permuted.value), "w": w.value}
+
+
+# ---------------------------------------------------------------------------
+# device side
+# ---------------------------------------------------------------------------
+
+def _stream_ptr(stream):
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype, numel, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a tensor on a HIP device")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Matrix:
+    """A device matrix (DA-CSR int16 or CSR int32) owned by the library."""
+
+    def __init__(self, handle, nrows, ncols, nnz, fmt, dtype):
+        self._h = handle
+        self.nrows, self.ncols, self.nnz = nrows, ncols, nnz
+        self.format, self.dtype = fmt, dtype
+
+    # construction -----------------------------------------------------------
+    @classmethod
+    def create(cls, nrows, ncols, rowptr, off, vals, store=F64, stream=None):
+        """Upload DA-CSR (int16 offsets) from host arrays."""
+        o = np.ascontiguousarray(off, dtype=np.int16)
+        v = np.ascontiguousarray(vals)
+        rp = _csr_arrays(nrows, rowptr, o, v)
+        vd = F32 if v.dtype == np.float32 else F64
+        v = v.astype(np.float64 if vd == F64 else np.float32, copy=False)
+        h = C.c_void_p()
+        _check(lib.damn_create(C.byref(h), nrows, ncols, _ptr(rp, C.c_int32), _ptr(o, C.c_int16),
+                               v.ctypes.data_as(C.c_void_p), vd, store, _stream_ptr(stream)),
+               "create")
+        return cls(h, nrows, ncols, int(rp[nrows]), FORMAT_DA16, store)
+
+    @classmethod
+    def csr_create(cls, nrows, ncols, rowptr, colids, vals, store=F64, stream=None):
+        """Upload plain CSR (int32 columns) from host arrays."""
+        c = _i32(colids)
+        v = np.ascontiguousarray(vals)
+        rp = _csr_arrays(nrows, rowptr, c, v)
+        vd = F32 if v.dtype == np.float32 else F64
+        v = v.astype(np.float64 if vd == F64 else np.float32, copy=False)
+        h = C.c_void_p()
+        _check(lib.damn_csr_create(C.byref(h), nrows, ncols, _ptr(rp, C.c_int32),
+                                   _ptr(c, C.c_int32), v.ctypes.data_as(C.c_void_p), vd, store,
+                                   _stream_ptr(stream)), "csr_create")
+        return cls(h, nrows, ncols, int(rp[nrows]), FORMAT_CSR32, store)
+
+    def destroy(self):
+        if self._h is not None and self._h.value:
+            _check(lib.damn_destroy(self._h), "destroy")
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def torch_dtype(self):
+        import torch
+
+        return torch.float64 if self.dtype == F64 else torch.float32
+
+    # products ---------------------------------------------------------------
+    def spmv(self, x, y, alpha=1.0, beta=0.0, stream=None):
+        """y <- alpha*A*x + beta*y (DA-CSR handle)."""
+        dt = self.torch_dtype
+        _check(lib.damn_spmv(self._h, _dev_ptr(x, dt, self.ncols, "x"),
+                             _dev_ptr(y, dt, self.nrows, "y"), float(alpha), float(beta),
+                             _stream_ptr(stream)), "spmv")
+
+    def csr_spmv(self, x, y, alpha=1.0, beta=0.0, stream=None):
+        """y <- alpha*A*x + beta*y (CSR handle)."""
+        dt = self.torch_dtype
+        _check(lib.damn_csr_spmv(self._h, _dev_ptr(x, dt, self.ncols, "x"),
+                                 _dev_ptr(y, dt, self.nrows, "y"), float(alpha), float(beta),
+                                 _stream_ptr(stream)), "csr_spmv")
+
+    def apply(self, x, y, alpha=1.0, beta=0.0, stream=None):
+        """spmv or csr_spmv, whichever matches the handle's format."""
+        f = self.spmv if self.format == FORMAT_DA16 else self.csr_spmv
+        f(x, y, alpha, beta, stream)
+
+    def spmm(self, X, Y, alpha=1.0, beta=0.0, stream=None):
+        """Y <- alpha*A*X + beta*Y; X (ncols, nrhs), Y (nrows, nrhs) row-major."""
+        import torch
+
+        if X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1]:
+            raise ValueError("X and Y must be 2-D with the same number of columns")
+        nrhs = int(X.shape[1])
+        _check(lib.damn_spmm(self._h, _dev_ptr(X, torch.float64, self.ncols * nrhs, "X"),
+                             _dev_ptr(Y, torch.float64, self.nrows * nrhs, "Y"), nrhs,
+                             float(alpha), float(beta), _stream_ptr(stream)), "spmm")
+
+    # configuration ----------------------------------------------------------
+    def set_config(self, variant=VAR_VECTOR, lanes=8, unroll=1, tile=2048):
+        cfg = _lib_config(variant, lanes, unroll, tile)
+        _check(lib.damn_set_config(self._h, C.addressof(cfg)), "set_config")
+
+    def get_config(self):
+        cfg = _Config()
+        _check(lib.damn_get_config(self._h, C.addressof(cfg)), "get_config")
+        return {"variant": cfg.variant, "lanes": cfg.lanes, "unroll": cfg.unroll,
+                "tile": cfg.tile}
+
+
+class _Config(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("lanes", C.c_int32), ("unroll", C.c_int32),
+                ("tile", C.c_int32)]
+
+
+def _lib_config(variant, lanes, unroll, tile):
+    return _Config(int(variant), int(lanes), int(unroll), int(tile))
+
+
+def stream_read(src, sink, stream=None):
+    """Streaming-read probe over a contiguous device tensor (bytes % 16 == 0);
+    sink: float64 device tensor with at least 65536 entries."""
+    import torch
+
+    if not src.is_cuda or not src.is_contiguous():
+        raise ValueError("src must be a contiguous device tensor")
+    nbytes = src.numel() * src.element_size()
+    _dev_ptr(sink, torch.float64, sink.numel(), "sink")
+    if sink.numel() < 65536:
+        raise ValueError("sink needs 65536 entries")
+    _check(lib.damn_stream_read(C.c_void_p(src.data_ptr()), C.c_size_t(nbytes),
+                                C.c_void_p(sink.data_ptr()), _stream_ptr(stream)), "stream_read")
+
+
+def library_path() -> str:
+    return os.path.abspath(LIB_PATH)

@@ -1,0 +1,65 @@
+"""Loading libdamn.so and declaring its C signatures (ctypes)."""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdamn.so")
+
+
+class DamnError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        try:
+            msg = lib.damn_status_string(int(code)).decode()
+        except Exception:  # library not loaded yet
+            msg = f"status {code}"
+        super().__init__(f"{what}: {msg} ({code})")
+
+
+class NoFit(Exception):
+    """Bandwidth >= 2^15, also after reordering; .w is the best bandwidth found."""
+
+    def __init__(self, w):
+        super().__init__(f"bandwidth {w} does not fit a 16-bit offset")
+        self.w = w
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2307_06305_amd.build`")
+    return C.CDLL(LIB_PATH)
+
+
+lib = _load()
+
+_i32, _i64, _f64, _vp = C.c_int32, C.c_int64, C.c_double, C.c_void_p
+_pi32, _pi16, _pf64 = C.POINTER(C.c_int32), C.POINTER(C.c_int16), C.POINTER(C.c_double)
+_pi64 = C.POINTER(C.c_int64)
+
+_SIGS = {
+    "damn_status_string": (C.c_char_p, [C.c_int]),
+    "damn_version": (C.c_char_p, []),
+    "damn_fit_check": (C.c_int, [_i32, _i32, _pi32, _pi32, _pi32, _pi32, _pi32, _pi32]),
+    "damn_rcm": (C.c_int, [_i32, _pi32, _pi32, _pi32]),
+    "damn_encode": (C.c_int, [_i32, _i32, _pi32, _pi32, _pf64, _i32, _pi32, _pi16, _pf64, _pi32,
+                              _pi32, _pi32]),
+    "damn_create": (C.c_int, [C.POINTER(_vp), _i32, _i32, _pi32, _pi16, _vp, _i32, _i32, _vp]),
+    "damn_csr_create": (C.c_int, [C.POINTER(_vp), _i32, _i32, _pi32, _pi32, _vp, _i32, _i32,
+                                  _vp]),
+    "damn_destroy": (C.c_int, [_vp]),
+    "damn_mat_info": (C.c_int, [_vp, _pi32, _pi32, _pi64, _pi32, _pi32]),
+    "damn_spmv": (C.c_int, [_vp, _vp, _vp, _f64, _f64, _vp]),
+    "damn_csr_spmv": (C.c_int, [_vp, _vp, _vp, _f64, _f64, _vp]),
+    "damn_spmm": (C.c_int, [_vp, _vp, _vp, _i32, _f64, _f64, _vp]),
+    "damn_set_config": (C.c_int, [_vp, _vp]),
+    "damn_get_config": (C.c_int, [_vp, _vp]),
+    "damn_stream_read": (C.c_int, [_vp, C.c_size_t, _vp, _vp]),
+}
+
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args

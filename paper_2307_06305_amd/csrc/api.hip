@@ -1,0 +1,356 @@
+// C ABI of libdamn.so: device matrices, products and configuration.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "damn.h"
+#include "damn_internal.h"
+#include "damn_kernels.h"
+
+struct damn_mat_s {
+  int device = 0;
+  int32_t nrows = 0, ncols = 0;
+  int64_t nnz = 0;
+  int32_t format = DAMN_FORMAT_DA16;
+  int32_t dtype = DAMN_F64;
+  int32_t* d_rowptr = nullptr;
+  void* d_idx = nullptr;
+  void* d_val = nullptr;
+  std::vector<int32_t> h_rowptr;  // host copy, for building stream tiles
+  damn_config cfg{};
+  int32_t* d_tiles = nullptr;
+  int64_t ntiles = 0;
+  int32_t tiles_cap = 0;
+};
+
+namespace damn {
+
+int host_threads() {
+  static int n = [] {
+    int t = int(std::thread::hardware_concurrency());
+    if (const char* e = std::getenv("DAMN_THREADS")) t = std::atoi(e);
+    if (t < 1) t = 1;
+    if (t > 64) t = 64;
+    return t;
+  }();
+  return n;
+}
+
+namespace {
+
+inline int64_t padded_entries(int64_t nnz) { return ((nnz + 7) / 8) * 8 + 16; }
+
+// Default launch shape from the mean row length: about as many lanes per
+// row as entries, so a row's loads are one coalesced access.
+damn_config default_config(int32_t nrows, int64_t nnz) {
+  damn_config c{};
+  c.variant = DAMN_VAR_VECTOR;
+  c.unroll = 1;
+  c.tile = 2048;
+  const double mean = nrows > 0 ? double(nnz) / nrows : 0.0;
+  int lanes = 1;
+  while (lanes < 64 && lanes < mean) lanes *= 2;
+  c.lanes = lanes;
+  return c;
+}
+
+bool valid_pow2_lanes(int32_t l) { return l >= 1 && l <= 64 && (l & (l - 1)) == 0; }
+
+void free_mat(damn_mat A) {
+  if (!A) return;
+  int cur = 0;
+  hipGetDevice(&cur);
+  hipSetDevice(A->device);
+  if (A->d_rowptr) hipFree(A->d_rowptr);
+  if (A->d_idx) hipFree(A->d_idx);
+  if (A->d_val) hipFree(A->d_val);
+  if (A->d_tiles) hipFree(A->d_tiles);
+  hipSetDevice(cur);
+  delete A;
+}
+
+// Cut rows into tiles of consecutive rows with at most `cap` entries and at
+// most kMaxTileRows rows; a longer row is a tile of its own.
+int build_tiles(damn_mat A, int32_t cap) {
+  if (A->d_tiles && A->tiles_cap == cap) return DAMN_OK;
+  std::vector<int32_t> starts;
+  try {
+    starts.reserve(size_t(A->nrows / 8 + 2));
+    const int32_t* rp = A->h_rowptr.data();
+    int32_t r = 0;
+    while (r < A->nrows) {
+      starts.push_back(r);
+      const int32_t first = r;
+      if (rp[r + 1] - rp[r] > cap) {
+        ++r;
+        continue;
+      }
+      while (r < A->nrows && r - first < kMaxTileRows && rp[r + 1] - rp[first] <= cap) ++r;
+    }
+    starts.push_back(A->nrows);
+  } catch (const std::bad_alloc&) {
+    return DAMN_ERR_ALLOC;
+  }
+  int32_t* d = nullptr;
+  if (hipMalloc(&d, sizeof(int32_t) * starts.size()) != hipSuccess) return DAMN_ERR_ALLOC;
+  if (hipMemcpy(d, starts.data(), sizeof(int32_t) * starts.size(), hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    hipFree(d);
+    return DAMN_ERR_HIP;
+  }
+  if (A->d_tiles) hipFree(A->d_tiles);
+  A->d_tiles = d;
+  A->ntiles = int64_t(starts.size()) - 1;
+  A->tiles_cap = cap;
+  return DAMN_OK;
+}
+
+int create_common(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* rowptr,
+                  const void* idx, size_t idx_size, const void* vals, int32_t vals_dtype,
+                  int32_t store_dtype, void* stream, int32_t format) {
+  if (out == nullptr || rowptr == nullptr) return DAMN_ERR_INVALID_ARG;
+  if ((vals_dtype != DAMN_F64 && vals_dtype != DAMN_F32) ||
+      (store_dtype != DAMN_F64 && store_dtype != DAMN_F32))
+    return DAMN_ERR_INVALID_ARG;
+  if (store_dtype == DAMN_F64 && vals_dtype == DAMN_F32) return DAMN_ERR_UNSUPPORTED;
+  const int64_t nnz = rowptr[nrows];
+  if (nnz > 0 && (idx == nullptr || vals == nullptr)) return DAMN_ERR_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  damn_mat A = nullptr;
+  try {
+    A = new damn_mat_s();
+    A->h_rowptr.assign(rowptr, rowptr + nrows + 1);
+  } catch (const std::bad_alloc&) {
+    delete A;
+    return DAMN_ERR_ALLOC;
+  }
+  hipGetDevice(&A->device);
+  A->nrows = nrows;
+  A->ncols = ncols;
+  A->nnz = nnz;
+  A->format = format;
+  A->dtype = store_dtype;
+  A->cfg = default_config(nrows, nnz);
+
+  const size_t vsize = store_dtype == DAMN_F64 ? 8 : 4;
+  const int64_t pe = padded_entries(nnz);
+  if (hipMalloc(&A->d_rowptr, sizeof(int32_t) * (size_t(nrows) + 1)) != hipSuccess ||
+      hipMalloc(&A->d_idx, idx_size * pe) != hipSuccess ||
+      hipMalloc(&A->d_val, vsize * pe) != hipSuccess) {
+    free_mat(A);
+    return DAMN_ERR_ALLOC;
+  }
+  std::vector<float> conv;
+  const void* src_vals = vals;
+  if (store_dtype == DAMN_F32 && vals_dtype == DAMN_F64) {
+    try {
+      conv.resize(size_t(nnz));
+    } catch (const std::bad_alloc&) {
+      free_mat(A);
+      return DAMN_ERR_ALLOC;
+    }
+    const double* v = static_cast<const double*>(vals);
+    parallel_for(nnz, [&](int64_t b, int64_t e) {
+      for (int64_t i = b; i < e; ++i) conv[i] = float(v[i]);  // round to nearest even
+    });
+    src_vals = conv.data();
+  }
+  bool ok = hipMemsetAsync(A->d_idx, 0, idx_size * pe, s) == hipSuccess &&
+            hipMemsetAsync(A->d_val, 0, vsize * pe, s) == hipSuccess &&
+            hipMemcpyAsync(A->d_rowptr, rowptr, sizeof(int32_t) * (size_t(nrows) + 1),
+                           hipMemcpyHostToDevice, s) == hipSuccess;
+  if (ok && nnz > 0)
+    ok = hipMemcpyAsync(A->d_idx, idx, idx_size * nnz, hipMemcpyHostToDevice, s) == hipSuccess &&
+         hipMemcpyAsync(A->d_val, src_vals, vsize * nnz, hipMemcpyHostToDevice, s) ==
+             hipSuccess;
+  if (ok) ok = hipStreamSynchronize(s) == hipSuccess;
+  if (!ok) {
+    free_mat(A);
+    return DAMN_ERR_HIP;
+  }
+  *out = A;
+  return DAMN_OK;
+}
+
+int run_spmv(damn_mat A, const void* x, void* y, double alpha, double beta, void* stream,
+             int32_t want_format) {
+  if (A == nullptr || A->format != want_format) return DAMN_ERR_INVALID_ARG;
+  if ((x == nullptr && A->ncols > 0 && alpha != 0.0) || (y == nullptr && A->nrows > 0))
+    return DAMN_ERR_INVALID_ARG;
+  SpmvArgs a;
+  a.nrows = A->nrows;
+  a.ncols = A->ncols;
+  a.rowptr = A->d_rowptr;
+  a.idx = A->d_idx;
+  a.val = A->d_val;
+  a.x = x;
+  a.y = y;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.read_y = beta != 0.0;
+  a.da = A->format == DAMN_FORMAT_DA16;
+  a.f32 = A->dtype == DAMN_F32;
+  a.stream = static_cast<hipStream_t>(stream);
+  if (A->cfg.variant == DAMN_VAR_STREAM) {
+    const int st = build_tiles(A, A->cfg.tile);
+    if (st != DAMN_OK) return st;
+    a.tile_row = A->d_tiles;
+    a.ntiles = A->ntiles;
+    a.cap = A->tiles_cap;
+  }
+  const hipError_t e = launch_spmv(a, A->cfg.variant, A->cfg.lanes, A->cfg.unroll);
+  return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
+}
+
+}  // namespace
+}  // namespace damn
+
+using namespace damn;
+
+extern "C" {
+
+const char* damn_status_string(int status) {
+  switch (status) {
+    case DAMN_OK: return "ok";
+    case DAMN_ERR_INVALID_ARG: return "invalid argument";
+    case DAMN_ERR_BAD_CSR: return "malformed CSR structure";
+    case DAMN_ERR_NO_FIT: return "bandwidth does not fit a 16-bit offset";
+    case DAMN_ERR_HIP: return "HIP runtime error";
+    case DAMN_ERR_ALLOC: return "allocation failed";
+    case DAMN_ERR_UNSUPPORTED: return "unsupported combination";
+    case DAMN_ERR_NOT_CONVERGED: return "iteration limit reached";
+    case DAMN_ERR_BREAKDOWN: return "breakdown: matrix not positive definite";
+    default: return "unknown status";
+  }
+}
+
+const char* damn_version(void) { return "damn 0.1.0 (gfx950)"; }
+
+int damn_create(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* rowptr,
+                const int16_t* off, const void* vals, int32_t vals_dtype, int32_t store_dtype,
+                void* stream) {
+  if (nrows < 0 || ncols < 0 || rowptr == nullptr) return DAMN_ERR_INVALID_ARG;
+  // structure, plus every r + off[i] inside [0, ncols)
+  if (rowptr[0] != 0) return DAMN_ERR_BAD_CSR;
+  for (int32_t r = 0; r < nrows; ++r)
+    if (rowptr[r + 1] < rowptr[r]) return DAMN_ERR_BAD_CSR;
+  const int64_t nnz = rowptr[nrows];
+  if (nnz > 0 && off == nullptr) return DAMN_ERR_INVALID_ARG;
+  int32_t bad = 0;
+  parallel_for(nrows, [&](int64_t b, int64_t e) {
+    int32_t local = 0;
+    for (int64_t r = b; r < e; ++r)
+      for (int64_t i = rowptr[r]; i < rowptr[r + 1]; ++i) {
+        const int64_t c = r + off[i];
+        local |= (c < 0) | (c >= ncols);
+      }
+    if (local) __atomic_store_n(&bad, 1, __ATOMIC_RELAXED);
+  }, 4096);
+  if (bad) return DAMN_ERR_BAD_CSR;
+  return create_common(out, nrows, ncols, rowptr, off, sizeof(int16_t), vals, vals_dtype,
+                       store_dtype, stream, DAMN_FORMAT_DA16);
+}
+
+int damn_csr_create(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* rowptr,
+                    const int32_t* colids, const void* vals, int32_t vals_dtype,
+                    int32_t store_dtype, void* stream) {
+  const int st = check_csr(nrows, ncols, rowptr, colids);
+  if (st != DAMN_OK) return st;
+  return create_common(out, nrows, ncols, rowptr, colids, sizeof(int32_t), vals, vals_dtype,
+                       store_dtype, stream, DAMN_FORMAT_CSR32);
+}
+
+int damn_destroy(damn_mat A) {
+  if (A == nullptr) return DAMN_ERR_INVALID_ARG;
+  int cur = 0;
+  hipGetDevice(&cur);
+  hipSetDevice(A->device);
+  hipDeviceSynchronize();
+  hipSetDevice(cur);
+  free_mat(A);
+  return DAMN_OK;
+}
+
+int damn_mat_info(damn_mat A, int32_t* nrows, int32_t* ncols, int64_t* nnz, int32_t* format,
+                  int32_t* dtype) {
+  if (A == nullptr) return DAMN_ERR_INVALID_ARG;
+  if (nrows) *nrows = A->nrows;
+  if (ncols) *ncols = A->ncols;
+  if (nnz) *nnz = A->nnz;
+  if (format) *format = A->format;
+  if (dtype) *dtype = A->dtype;
+  return DAMN_OK;
+}
+
+int damn_spmv(damn_mat A, const void* x, void* y, double alpha, double beta, void* stream) {
+  return run_spmv(A, x, y, alpha, beta, stream, DAMN_FORMAT_DA16);
+}
+
+int damn_csr_spmv(damn_mat A, const void* x, void* y, double alpha, double beta,
+                  void* stream) {
+  return run_spmv(A, x, y, alpha, beta, stream, DAMN_FORMAT_CSR32);
+}
+
+int damn_spmm(damn_mat A, const void* X, void* Y, int32_t nrhs, double alpha, double beta,
+              void* stream) {
+  if (A == nullptr || nrhs < 1) return DAMN_ERR_INVALID_ARG;
+  if (nrhs > 8) return DAMN_ERR_UNSUPPORTED;
+  if (A->dtype != DAMN_F64) return DAMN_ERR_UNSUPPORTED;
+  if ((X == nullptr && A->ncols > 0 && alpha != 0.0) || (Y == nullptr && A->nrows > 0))
+    return DAMN_ERR_INVALID_ARG;
+  SpmvArgs a;
+  a.nrows = A->nrows;
+  a.ncols = A->ncols;
+  a.rowptr = A->d_rowptr;
+  a.idx = A->d_idx;
+  a.val = A->d_val;
+  a.x = X;
+  a.y = Y;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.read_y = beta != 0.0;
+  a.da = A->format == DAMN_FORMAT_DA16;
+  a.stream = static_cast<hipStream_t>(stream);
+  const hipError_t e = launch_spmm(a, A->cfg.lanes, nrhs);
+  return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
+}
+
+int damn_set_config(damn_mat A, const damn_config* cfg) {
+  if (A == nullptr || cfg == nullptr) return DAMN_ERR_INVALID_ARG;
+  if (cfg->variant != DAMN_VAR_VECTOR && cfg->variant != DAMN_VAR_STREAM)
+    return DAMN_ERR_INVALID_ARG;
+  if (!valid_pow2_lanes(cfg->lanes)) return DAMN_ERR_INVALID_ARG;
+  damn_config c = *cfg;
+  if (c.variant == DAMN_VAR_VECTOR) {
+    if (c.unroll != 1 && c.unroll != 2 && c.unroll != 4) return DAMN_ERR_INVALID_ARG;
+    if (c.tile == 0) c.tile = A->cfg.tile;
+  } else {
+    if (c.tile < 256 || c.tile > 4096 || (c.tile % 8) != 0) return DAMN_ERR_UNSUPPORTED;
+    if (c.unroll == 0) c.unroll = 1;
+    const int st = build_tiles(A, c.tile);
+    if (st != DAMN_OK) return st;
+  }
+  A->cfg = c;
+  return DAMN_OK;
+}
+
+int damn_get_config(damn_mat A, damn_config* cfg) {
+  if (A == nullptr || cfg == nullptr) return DAMN_ERR_INVALID_ARG;
+  *cfg = A->cfg;
+  return DAMN_OK;
+}
+
+int damn_stream_read(const void* src, size_t bytes, double* sink, void* stream) {
+  if ((src == nullptr && bytes > 0) || sink == nullptr || bytes % 16 != 0)
+    return DAMN_ERR_INVALID_ARG;
+  const hipError_t e =
+      launch_stream_read(src, int64_t(bytes), sink, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
+}
+
+}  // extern "C"

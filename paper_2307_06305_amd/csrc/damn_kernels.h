@@ -1,0 +1,39 @@
+// Launch interface between the C ABI layer and the product kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace damn {
+
+// Rows per stream tile are capped so one workgroup's second step stays short.
+constexpr int32_t kMaxTileRows = 2048;
+
+struct SpmvArgs {
+  int32_t nrows = 0;
+  int32_t ncols = 0;
+  const int32_t* rowptr = nullptr;
+  const void* idx = nullptr;  // int16 offsets (da) or int32 columns
+  const void* val = nullptr;  // float64 or float32 (f32)
+  const void* x = nullptr;
+  void* y = nullptr;
+  double alpha = 1.0;
+  double beta = 0.0;
+  int32_t read_y = 0;  // beta != 0
+  bool da = true;
+  bool f32 = false;
+  // stream variant
+  const int32_t* tile_row = nullptr;
+  int64_t ntiles = 0;
+  int32_t cap = 0;
+  hipStream_t stream = nullptr;
+};
+
+// variant 0 = vector (lanes, unroll), 1 = stream (lanes = G, tiles in args)
+hipError_t launch_spmv(const SpmvArgs& a, int variant, int lanes, int unroll);
+// float64 only; 1 <= nrhs <= 8
+hipError_t launch_spmm(const SpmvArgs& a, int lanes, int nrhs);
+hipError_t launch_stream_read(const void* src, int64_t bytes, double* sink, hipStream_t s);
+
+}  // namespace damn

@@ -1,0 +1,265 @@
+"""GPU parity of the HIP SpMV / SpMM kernels against the CPU oracle, through
+the C ABI.  Every launch configuration the library accepts is checked."""
+
+import numpy as np
+import pytest
+
+import paper_2307_06305_amd as D
+from gpu_util import U32, U64, assert_within, dev, error_bound, host, torch_or_skip
+from oracle import spmv as OS
+from oracle import storage as OST
+from paper_2307_06305_amd.tuning import candidates, config_name
+from workloads import (config_matrix, laplace_2d_5pt, poisson_3d_7pt, random_banded, random_csr,
+                       stencil_3d_27pt, uniform_vector)
+
+pytestmark = pytest.mark.gpu
+
+
+def _long_rows():
+    # rows far longer than any tile cap, mixed with empty and short rows
+    rng = np.random.default_rng(5)
+    ncols = 9000
+    rl = np.array([0, 5000, 1, 0, 7000, 3] * 6 + [4100, 0], dtype=np.int64)
+    nrows = rl.size
+    rp = np.zeros(nrows + 1, dtype=np.int64)
+    np.cumsum(rl, out=rp[1:])
+    cols = np.concatenate([np.sort(rng.choice(ncols, size=k, replace=False)) for k in rl])
+    from workloads.matrices import CSR
+    return CSR(nrows, ncols, rp.astype(np.int32), cols.astype(np.int32),
+               rng.uniform(-1, 1, int(rp[-1])), "long_rows")
+
+
+def _matrices():
+    yield config_matrix(0)                                   # 2D 5-point 64x64
+    yield stencil_3d_27pt(20, 11)                            # 27-point, 8000 rows
+    yield random_banded(30000, 12, half_band=3000)           # lognormal rows
+    yield random_csr(700, 300, 3, mean_len=6, band=250, empty_frac=0.2, dup_frac=0.1,
+                     zero_frac=0.1, shuffle_rows=True)        # tall
+    yield random_csr(300, 700, 4, mean_len=9, band=500, empty_frac=0.2, dup_frac=0.1)  # wide
+    yield _long_rows()
+
+
+MATS = list(_matrices())
+
+
+def _encode(A):
+    e = D.encode(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, allow_rcm=False)
+    return e
+
+
+@pytest.mark.parametrize("fmt", ["da", "csr"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("A", MATS, ids=lambda A: A.name)
+def test_spmv_all_configs_match_oracle(A, dtype, fmt):
+    torch = torch_or_skip()
+    print(f"case {A.name} {dtype} {fmt}", flush=True)
+    f32 = dtype == "f32"
+    vals = A.vals.astype(np.float32) if f32 else A.vals
+    x = uniform_vector(A.ncols, 77)
+    y0 = uniform_vector(A.nrows, 78)
+    if f32:
+        x, y0 = x.astype(np.float32), y0.astype(np.float32)
+    store = D.F32 if f32 else D.F64
+    if fmt == "da":
+        e = _encode(A)
+        M = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], vals, store=store)
+    else:
+        M = D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, vals, store=store)
+    tdt = torch.float32 if f32 else torch.float64
+    xd = dev(x, tdt)
+    u = U32 if f32 else U64
+    for alpha, beta in ((1.0, 0.0), (-0.75, 1.5)):
+        ref = OS.spmv_csr(A.nrows, A.ncols, A.rowptr, A.colids, vals, x, alpha, beta, y0)
+        bnd = error_bound(A.nrows, A.rowptr, A.colids, vals, x, alpha, beta, y0, u)
+        for cfg in candidates():
+            yd = dev(y0, tdt)
+            M.set_config(*cfg)
+            M.apply(xd, yd, alpha, beta)
+            assert_within(host(yd), ref, bnd, f"{A.name} {fmt} {dtype} {config_name(cfg)} "
+                                              f"alpha={alpha} beta={beta}")
+    M.destroy()
+
+
+def _grid_quadratic(shape):
+    idx = np.indices(shape[::-1])[::-1]  # x fastest
+    return sum(a.astype(np.float64) ** 2 for a in idx).ravel(), idx
+
+
+def _ghost_sum(shape, idx):
+    """Sum over missing (off-grid) neighbours of the quadratic's values."""
+    out = np.zeros(int(np.prod(shape)))
+    for axis, n in enumerate(shape):
+        for step in (-1, 1):
+            coords = [a.ravel().astype(np.float64) for a in idx]
+            c = coords[axis] + step
+            missing = (c < 0) | (c >= n)
+            coords[axis] = c
+            val = sum(v ** 2 for v in coords)
+            out += np.where(missing, val, 0.0)
+    return out
+
+
+@pytest.mark.parametrize("fmt", ["da", "csr"])
+def test_laplace_2d_closed_forms_bit_exact(fmt):
+    torch = torch_or_skip()
+    N = 64
+    A = laplace_2d_5pt(N)
+    e = _encode(A)
+    M = (D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], A.vals) if fmt == "da"
+         else D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals))
+    # stencil times ones = row sums: 0 inside, 1 on edges, 2 in corners
+    idx = np.indices((N, N))[::-1]
+    on_edge = (idx[0] == 0).astype(int) + (idx[0] == N - 1) + (idx[1] == 0) + (idx[1] == N - 1)
+    expect_ones = on_edge.ravel().astype(np.float64)
+    f, idx2 = _grid_quadratic((N, N))
+    expect_quad = -4.0 + _ghost_sum((N, N), idx2)
+    for cfg in candidates():
+        M.set_config(*cfg)
+        for vec, expect in ((np.ones(N * N), expect_ones), (f, expect_quad)):
+            yd = dev(np.zeros(N * N))
+            M.apply(dev(vec), yd)
+            assert np.array_equal(host(yd), expect), config_name(cfg)
+    M.destroy()
+
+
+@pytest.mark.parametrize("fmt", ["da", "csr"])
+def test_poisson_3d_quadratic_bit_exact(fmt):
+    torch = torch_or_skip()
+    shape = (12, 10, 14)
+    A = poisson_3d_7pt(*shape)
+    e = _encode(A)
+    M = (D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], A.vals) if fmt == "da"
+         else D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals))
+    f, idx = _grid_quadratic(shape)
+    expect = -6.0 + _ghost_sum(shape, idx)
+    for cfg in candidates():
+        M.set_config(*cfg)
+        yd = dev(np.zeros(A.nrows))
+        M.apply(dev(f), yd)
+        assert np.array_equal(host(yd), expect), config_name(cfg)
+    M.destroy()
+
+
+def test_beta_zero_ignores_nan_and_alpha_zero_scales():
+    torch = torch_or_skip()
+    A = stencil_3d_27pt(8, 2)
+    e = _encode(A)
+    M = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], A.vals)
+    x = uniform_vector(A.ncols, 1)
+    ref = OS.spmv_csr(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, x)
+    bnd = error_bound(A.nrows, A.rowptr, A.colids, A.vals, x, 1.0, 0.0, None, U64)
+    y0 = uniform_vector(A.nrows, 2)
+    for cfg in candidates():
+        M.set_config(*cfg)
+        yd = dev(np.full(A.nrows, np.nan))
+        M.spmv(dev(x), yd, 1.0, 0.0)
+        assert_within(host(yd), ref, bnd, config_name(cfg))
+        # alpha = 0: y <- beta*y exactly, x not read (NaN x is harmless)
+        yd = dev(y0)
+        M.spmv(dev(np.full(A.ncols, np.nan)), yd, 0.0, 2.0)
+        assert np.array_equal(host(yd), 2.0 * y0)
+        yd = dev(y0)
+        M.spmv(dev(x), yd, 0.0, 0.0)
+        assert np.array_equal(host(yd), np.zeros(A.nrows))
+    M.destroy()
+
+
+def test_empty_shapes():
+    torch = torch_or_skip()
+    # nnz = 0 with rows: y = beta*y0 exactly; zero rows: nothing to do
+    for nrows, ncols in ((50, 20), (0, 10), (10, 0)):
+        rp = np.zeros(nrows + 1, dtype=np.int32)
+        M = D.Matrix.create(nrows, ncols, rp, np.zeros(0, np.int16), np.zeros(0))
+        C = D.Matrix.csr_create(nrows, ncols, rp, np.zeros(0, np.int32), np.zeros(0))
+        y0 = uniform_vector(nrows, 3)
+        for cfg in candidates():
+            for mat in (M, C):
+                mat.set_config(*cfg)
+                yd = dev(y0)
+                mat.apply(dev(np.ones(ncols)), yd, 1.0, 0.5)
+                assert np.array_equal(host(yd), 0.5 * y0)
+        M.destroy()
+        C.destroy()
+
+
+@pytest.mark.parametrize("fmt", ["da", "csr"])
+@pytest.mark.parametrize("A", MATS[:4], ids=lambda A: A.name)
+def test_spmm_matches_oracle(A, fmt):
+    torch = torch_or_skip()
+    e = _encode(A)
+    M = (D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], A.vals) if fmt == "da"
+         else D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals))
+    for nrhs in range(1, 9):
+        X = uniform_vector(A.ncols, 10 + nrhs, nrhs)
+        Y0 = uniform_vector(A.nrows, 20 + nrhs, nrhs)
+        for alpha, beta in ((1.0, 0.0), (2.0, -1.0)):
+            ref = OS.spmm_csr(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, X, alpha, beta, Y0)
+            for lanes in (1, 4, 8, 32, 64):
+                M.set_config(0, lanes, 1, 2048)
+                Yd = dev(Y0)
+                M.spmm(dev(X), Yd, alpha, beta)
+                Y = host(Yd)
+                for j in range(nrhs):
+                    bnd = error_bound(A.nrows, A.rowptr, A.colids, A.vals, X[:, j], alpha, beta,
+                                      Y0[:, j], U64)
+                    assert_within(Y[:, j], ref[:, j], bnd, f"{A.name} nrhs={nrhs} lanes={lanes}")
+    M.destroy()
+
+
+def test_invalid_calls_return_status():
+    torch = torch_or_skip()
+    A = laplace_2d_5pt(8)
+    e = _encode(A)
+    M = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], A.vals)
+    C = D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals)
+    x, y = dev(np.ones(64)), dev(np.zeros(64))
+    with pytest.raises(D.DamnError):
+        M.csr_spmv(x, y)          # DA handle through the CSR entry point
+    with pytest.raises(D.DamnError):
+        C.spmv(x, y)              # and the reverse
+    X, Y = dev(np.ones((64, 9))), dev(np.zeros((64, 9)))
+    with pytest.raises(D.DamnError) as ei:
+        M.spmm(X, Y)
+    assert ei.value.code == -6
+    with pytest.raises(D.DamnError):
+        M.set_config(0, 3, 1, 2048)  # lanes not a power of two
+    with pytest.raises(D.DamnError):
+        M.set_config(1, 8, 1, 100)   # tile too small
+    # offsets that would read outside x are refused at upload
+    with pytest.raises(D.DamnError) as ei:
+        D.Matrix.create(2, 2, [0, 1, 2], np.array([1, 1], np.int16), np.ones(2))
+    assert ei.value.code == -2
+    M.destroy()
+    C.destroy()
+
+
+def test_full_size_27pt_sampled_rows():
+    """The 128^3 27-point matrix in every configuration: sampled rows against
+    the oracle computed row by row."""
+    torch = torch_or_skip()
+    A = config_matrix(1)
+    e = _encode(A)
+    assert e["w"] == 16513
+    M = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], A.vals)
+    C = D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals)
+    x = uniform_vector(A.ncols, 2001)
+    xd = dev(x)
+    rng = np.random.default_rng(0)
+    rows = np.unique(np.concatenate([rng.integers(0, A.nrows, 3000), [0, A.nrows - 1]]))
+    # the sampled rows as a matrix of their own, for the oracle
+    starts, ends = A.rowptr[rows].astype(np.int64), A.rowptr[rows + 1].astype(np.int64)
+    rl = ends - starts
+    sub_rp = np.concatenate([[0], np.cumsum(rl)]).astype(np.int32)
+    take = np.concatenate([np.arange(s, t) for s, t in zip(starts, ends)])
+    sub_c, sub_v = A.colids[take], A.vals[take]
+    ref = OS.spmv_csr(rows.size, A.ncols, sub_rp, sub_c, sub_v, x)
+    bnd = error_bound(rows.size, sub_rp, sub_c, sub_v, x, 1.0, 0.0, None, U64)
+    for mat in (M, C):
+        for cfg in candidates():
+            yd = torch.zeros(A.nrows, dtype=torch.float64, device="cuda")
+            mat.set_config(*cfg)
+            mat.apply(xd, yd)
+            y = host(yd)[rows]
+            assert_within(y, ref, bnd, config_name(cfg))
+    M.destroy()
+    C.destroy()

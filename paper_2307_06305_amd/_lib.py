@@ -27,6 +27,13 @@ class NoFit(Exception):
 
 
 def _load():
+    # torch ships its own HIP runtime with the same soname as ROCm's
+    # (libamdhip64.so.7).  Loading torch first makes libdamn.so bind to that
+    # runtime, so device pointers and streams from torch are valid in the
+    # library; loading the library first would put two HIP runtimes in the
+    # process.
+    import torch  # noqa: F401
+
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python -m paper_2307_06305_amd.build`")

@@ -81,6 +81,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tune-reps", type=int, default=10)
+    ap.add_argument("--dump", default=None, help="write the autotuner's timing table here (JSON)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
@@ -128,6 +129,11 @@ def main():
     best_csr, times_csr = autotune(Cm, xd, yc, reps=args.tune_reps)
     log(f"DA best {config_name(best_da)} {times_da[best_da]*1e6:.1f}us; "
         f"CSR best {config_name(best_csr)} {times_csr[best_csr]*1e6:.1f}us")
+    if args.dump:
+        with open(args.dump, "w") as f:
+            json.dump({"da": {config_name(c): t * 1e6 for c, t in sorted(times_da.items(), key=lambda kv: kv[1])},
+                       "csr": {config_name(c): t * 1e6 for c, t in sorted(times_csr.items(), key=lambda kv: kv[1])}},
+                      f, indent=1)
 
     T_da = model_bytes(A.nrows, A.ncols, A.nnz, 2)
     T_csr = model_bytes(A.nrows, A.ncols, A.nnz, 4)

@@ -44,16 +44,17 @@ namespace {
 
 inline int64_t padded_entries(int64_t nnz) { return ((nnz + 7) / 8) * 8 + 16; }
 
-// Default launch shape from the mean row length: about as many lanes per
-// row as entries, so a row's loads are one coalesced access.
+// Default launch shape: the stream variant with 2048-entry tiles; one lane
+// per row for very short rows, two otherwise, and more lanes for long rows
+// (about one lane per 16 entries).
 damn_config default_config(int32_t nrows, int64_t nnz) {
   damn_config c{};
-  c.variant = DAMN_VAR_VECTOR;
+  c.variant = DAMN_VAR_STREAM;
   c.unroll = 1;
   c.tile = 2048;
   const double mean = nrows > 0 ? double(nnz) / nrows : 0.0;
-  int lanes = 1;
-  while (lanes < 64 && lanes < mean) lanes *= 2;
+  int lanes = mean < 4.0 ? 1 : 2;
+  while (lanes < 64 && lanes * 16 < mean) lanes *= 2;
   c.lanes = lanes;
   return c;
 }

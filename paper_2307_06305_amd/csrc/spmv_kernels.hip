@@ -86,41 +86,37 @@ __global__ __launch_bounds__(256) void spmv_vector(
 // Stream variant.  The host cuts the rows into tiles of consecutive rows
 // holding at most `cap` entries (and at most kMaxTileRows rows); a row longer
 // than `cap` is a tile of its own.  A workgroup:
-//   1. streams the tile's indices and values into LDS with aligned 16-byte
-//      loads (8 entries per thread per step, starting at the tile's first
-//      entry rounded down to a multiple of 8);
+//   1. copies the tile's indices and values from HBM straight into LDS with
+//      16-byte direct-to-LDS loads (global_load_lds_dwordx4), starting at the
+//      tile's first entry rounded down to a multiple of 8.  The loads carry
+//      the non-temporal hint: the matrix is read once, and keeping it from
+//      displacing x in L2 means each x line is fetched from HBM once;
 //   2. reduces each row from LDS with G lanes per row, gathering x.
-// Step 1 runs at full load width whatever the row lengths; step 2 puts
+// Step 1 streams at full load width whatever the row lengths; step 2 puts
 // neighbouring rows on neighbouring lanes, so for banded matrices the x
 // gathers of one instruction hit few cache lines.
 // ---------------------------------------------------------------------------
-template <typename T>
-struct Chunk8;  // 8 consecutive entries as 16-byte pieces
-template <>
-struct Chunk8<int16_t> {
-  static constexpr int kPieces = 1;
-};
-template <>
-struct Chunk8<int32_t> {
-  static constexpr int kPieces = 2;
-};
-template <>
-struct Chunk8<float> {
-  static constexpr int kPieces = 2;
-};
-template <>
-struct Chunk8<double> {
-  static constexpr int kPieces = 4;
-};
-
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+constexpr int kNonTemporal = 2;  // cache-policy bit "nt" of gfx950 loads
+
+// Issue direct-to-LDS copies of elements [a0, a0 + n) of src (a0 a multiple
+// of 8) into dst[0, ...), 16 bytes per lane.  Lane l of wave w copies piece
+// 64*(w + 4*j) + l; every wave writes 1 KiB contiguous blocks of LDS.
 template <typename T>
-__device__ __forceinline__ void copy_chunk8(T* __restrict__ dst, const T* __restrict__ src) {
-  const u32x4* s = reinterpret_cast<const u32x4*>(src);
-  u32x4* d = reinterpret_cast<u32x4*>(dst);
-#pragma unroll
-  for (int k = 0; k < Chunk8<T>::kPieces; ++k) d[k] = __builtin_nontemporal_load(s + k);
+__device__ __forceinline__ void copy_to_lds(T* __restrict__ dst, const T* __restrict__ src,
+                                            int32_t a0, int32_t n) {
+#if defined(__HIP_DEVICE_COMPILE__)  // the builtin exists only in the device pass
+  constexpr int32_t kPer = 16 / int32_t(sizeof(T));  // elements per piece
+  const int32_t pieces = (n + kPer - 1) / kPer;
+  const int32_t wave = int32_t(threadIdx.x >> 6), lane = int32_t(threadIdx.x & 63);
+  for (int32_t base = wave * 64; base < pieces; base += 256) {
+    const int32_t q = base + lane;
+    if (q < pieces)
+      __builtin_amdgcn_global_load_lds(src + a0 + kPer * q, dst + kPer * base, 16, 0,
+                                       kNonTemporal);
+  }
+#endif
 }
 
 template <typename I, typename V, bool DA, int G>
@@ -152,13 +148,14 @@ __global__ __launch_bounds__(256) void spmv_stream(
     return;
   }
 
-  // 1. stream [a0, p1) into LDS, 8 entries per thread per step
+  // 1. [a0, p1) into LDS (a0 = p0 rounded down to 8 entries; at most
+  //    cap + 7 entries plus the rounding of the last piece, within cap + 16)
   const int32_t a0 = p0 & ~7;
-  const int32_t nchunk = (p1 - a0 + 7) >> 3;
-  for (int32_t c = threadIdx.x; c < nchunk; c += 256) {
-    copy_chunk8(idx_s + 8 * c, idx + (a0 + 8 * c));
-    copy_chunk8(val_s + 8 * c, val + (a0 + 8 * c));
-  }
+  copy_to_lds(val_s, val, a0, p1 - a0);
+  copy_to_lds(idx_s, idx, a0, p1 - a0);
+  // the direct-to-LDS writes are tracked by vmcnt; the memory clobber keeps
+  // the compiler from moving LDS reads above the wait
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 
   // 2. G lanes per row
@@ -166,14 +163,16 @@ __global__ __launch_bounds__(256) void spmv_stream(
   for (int32_t r = r0 + int32_t(threadIdx.x / G); r < r1; r += 256 / G) {
     const int32_t s = rowptr[r] - a0, e = rowptr[r + 1] - a0;
     const V* xs = DA ? x + r : x;
-    V acc0 = V(0), acc1 = V(0);
+    V acc[4] = {V(0), V(0), V(0), V(0)};
     int32_t k = s + lane;
-    for (; k + G < e; k += 2 * G) {
-      acc0 += val_s[k] * xs[idx_s[k]];
-      acc1 += val_s[k + G] * xs[idx_s[k + G]];
+    for (; k + 3 * G < e; k += 4 * G) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += val_s[k + u * G] * xs[idx_s[k + u * G]];
     }
-    if (k < e) acc0 += val_s[k] * xs[idx_s[k]];
-    V sum = acc0 + acc1;
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+      if (k + u * G < e) acc[u] += val_s[k + u * G] * xs[idx_s[k + u * G]];
+    V sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     if (G > 1) sum = group_sum(sum, G);
     if (lane == 0) y[r] = finish(sum, alpha, beta, read_y != 0, y + r);
   }

@@ -197,6 +197,46 @@ int damn_set_config(damn_mat A, const damn_config* cfg);
 int damn_get_config(damn_mat A, damn_config* cfg);
 
 /* ------------------------------------------------------------------------
+ * Conjugate gradients on the device (the iterative solvers the paper's DA
+ * storage is meant for, Sec. 3 footnote; the multi-precision argument of the
+ * remark after Fig. 3: a DA-CSR int16 matrix gains 5/3x traffic when its
+ * scalars go from float64 to float32, against 3/2x for CSR int32).
+ * --------------------------------------------------------------------- */
+
+typedef struct {
+  double tol;          /* stop when ||b - A x||_2 <= tol * ||b||_2 (1e-10)   */
+  double inner_tol;    /* mixed: inner solve to relative residual (1e-5)    */
+  int32_t max_iter;    /* CG iterations (mixed: per inner solve)            */
+  int32_t max_outer;   /* mixed: refinement steps (50)                      */
+  int32_t check_every; /* iterations between host reads of the stop flag    */
+} damn_cg_opts;
+
+typedef struct {
+  int32_t iters;     /* float64 CG: iterations; mixed: inner iterations, all */
+  int32_t outer;     /* mixed: refinement steps taken                        */
+  int32_t converged; /* 1 if the residual target was met                    */
+  double rel_res;    /* ||b - A x|| / ||b|| of the returned x, float64       */
+} damn_cg_info;
+
+/* Solve A x = b for symmetric positive definite A, from x0 = 0.
+ * A64: float64 handle (DA-CSR or CSR), square.  A32 == NULL: float64 CG
+ * (Hestenes-Stiefel; vectors and dot products float64; stops on the
+ * recursively updated residual, then reports the true residual).
+ * A32 != NULL: mixed precision with iterative refinement.  A32 is the same
+ * matrix with float32 values (same format and shape).  Each outer step forms
+ * r = b - A64 x and ||r|| in float64; if not yet converged it runs CG on
+ * A32 d = r/||r|| with float32 vectors, float32-accumulated products with
+ * A32 and float64-accumulated dot products, to inner_tol, then x += ||r|| d.
+ * b, x: device float64 vectors of n entries (x is overwritten; on
+ * DAMN_ERR_NOT_CONVERGED / DAMN_ERR_BREAKDOWN it holds the last iterate).
+ * The call synchronises `stream` (it reads the stop flag every check_every
+ * iterations).  Device workspace (about 7 vectors) is kept with A64.
+ * Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_NOT_CONVERGED (limits reached),
+ *         DAMN_ERR_BREAKDOWN (p.Ap <= 0), DAMN_ERR_ALLOC, DAMN_ERR_HIP. */
+int damn_cg(damn_mat A64, damn_mat A32, const double* b, double* x,
+            const damn_cg_opts* opts, damn_cg_info* info, void* stream);
+
+/* ------------------------------------------------------------------------
  * Measurement helpers.
  * --------------------------------------------------------------------- */
 

@@ -241,6 +241,37 @@ def _lib_config(variant, lanes, unroll, tile):
     return _Config(int(variant), int(lanes), int(unroll), int(tile))
 
 
+class _CgOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("inner_tol", C.c_double), ("max_iter", C.c_int32),
+                ("max_outer", C.c_int32), ("check_every", C.c_int32)]
+
+
+class _CgInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("outer", C.c_int32), ("converged", C.c_int32),
+                ("rel_res", C.c_double)]
+
+
+def cg(A64, b, x, A32=None, tol=1e-10, inner_tol=1e-5, max_iter=20000, max_outer=50,
+       check_every=16, stream=None):
+    """Solve A x = b on the device (float64 CG, or mixed precision when A32,
+    the float32-valued copy, is given).  b, x: float64 device vectors.
+    Returns dict(iters, outer, converged, rel_res); raises DamnError on
+    breakdown or invalid input (not on reaching the iteration limit)."""
+    import torch
+
+    n = A64.nrows
+    opts = _CgOpts(float(tol), float(inner_tol), int(max_iter), int(max_outer),
+                   int(check_every))
+    info = _CgInfo()
+    st = lib.damn_cg(A64.handle, None if A32 is None else A32.handle,
+                     _dev_ptr(b, torch.float64, n, "b"), _dev_ptr(x, torch.float64, n, "x"),
+                     C.addressof(opts), C.addressof(info), _stream_ptr(stream))
+    if st not in (0, -7):
+        raise DamnError(st, "cg")
+    return {"iters": info.iters, "outer": info.outer, "converged": bool(info.converged),
+            "rel_res": info.rel_res}
+
+
 def stream_read(src, sink, stream=None):
     """Streaming-read probe over a contiguous device tensor (bytes % 16 == 0);
     sink: float64 device tensor with at least 65536 entries."""

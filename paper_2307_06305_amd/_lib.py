@@ -40,8 +40,6 @@ def _load():
     return C.CDLL(LIB_PATH)
 
 
-lib = _load()
-
 _i32, _i64, _f64, _vp = C.c_int32, C.c_int64, C.c_double, C.c_void_p
 _pi32, _pi16, _pf64 = C.POINTER(C.c_int32), C.POINTER(C.c_int16), C.POINTER(C.c_double)
 _pi64 = C.POINTER(C.c_int64)
@@ -64,9 +62,28 @@ _SIGS = {
     "damn_set_config": (C.c_int, [_vp, _vp]),
     "damn_get_config": (C.c_int, [_vp, _vp]),
     "damn_stream_read": (C.c_int, [_vp, C.c_size_t, _vp, _vp]),
+    "damn_cg": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
 }
 
-for _name, (_res, _args) in _SIGS.items():
-    _f = getattr(lib, _name)
-    _f.restype = _res
-    _f.argtypes = _args
+class _Lib:
+    """libdamn.so, loaded on first use (so the build step can import this
+    package before the library exists); raises ImportError if it is missing."""
+
+    def __init__(self):
+        self._cdll = None
+
+    def _get(self):
+        if self._cdll is None:
+            cdll = _load()
+            for name, (res, args) in _SIGS.items():
+                f = getattr(cdll, name)
+                f.restype = res
+                f.argtypes = args
+            self._cdll = cdll
+        return self._cdll
+
+    def __getattr__(self, name):
+        return getattr(self._get(), name)
+
+
+lib = _Lib()

@@ -10,24 +10,45 @@
 #include "damn.h"
 #include "damn_internal.h"
 #include "damn_kernels.h"
-
-struct damn_mat_s {
-  int device = 0;
-  int32_t nrows = 0, ncols = 0;
-  int64_t nnz = 0;
-  int32_t format = DAMN_FORMAT_DA16;
-  int32_t dtype = DAMN_F64;
-  int32_t* d_rowptr = nullptr;
-  void* d_idx = nullptr;
-  void* d_val = nullptr;
-  std::vector<int32_t> h_rowptr;  // host copy, for building stream tiles
-  damn_config cfg{};
-  int32_t* d_tiles = nullptr;
-  int64_t ntiles = 0;
-  int32_t tiles_cap = 0;
-};
+#include "damn_mat.h"
 
 namespace damn {
+
+// Cut rows into tiles of consecutive rows with at most `cap` entries and at
+// most kMaxTileRows rows; a longer row is a tile of its own.
+int build_tiles(damn_mat A, int32_t cap) {
+  if (A->d_tiles && A->tiles_cap == cap) return DAMN_OK;
+  std::vector<int32_t> starts;
+  try {
+    starts.reserve(size_t(A->nrows / 8 + 2));
+    const int32_t* rp = A->h_rowptr.data();
+    int32_t r = 0;
+    while (r < A->nrows) {
+      starts.push_back(r);
+      const int32_t first = r;
+      if (rp[r + 1] - rp[r] > cap) {
+        ++r;
+        continue;
+      }
+      while (r < A->nrows && r - first < kMaxTileRows && rp[r + 1] - rp[first] <= cap) ++r;
+    }
+    starts.push_back(A->nrows);
+  } catch (const std::bad_alloc&) {
+    return DAMN_ERR_ALLOC;
+  }
+  int32_t* d = nullptr;
+  if (hipMalloc(&d, sizeof(int32_t) * starts.size()) != hipSuccess) return DAMN_ERR_ALLOC;
+  if (hipMemcpy(d, starts.data(), sizeof(int32_t) * starts.size(), hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    hipFree(d);
+    return DAMN_ERR_HIP;
+  }
+  if (A->d_tiles) hipFree(A->d_tiles);
+  A->d_tiles = d;
+  A->ntiles = int64_t(starts.size()) - 1;
+  A->tiles_cap = cap;
+  return DAMN_OK;
+}
 
 int host_threads() {
   static int n = [] {
@@ -70,44 +91,9 @@ void free_mat(damn_mat A) {
   if (A->d_idx) hipFree(A->d_idx);
   if (A->d_val) hipFree(A->d_val);
   if (A->d_tiles) hipFree(A->d_tiles);
+  release_cg_work(A);
   hipSetDevice(cur);
   delete A;
-}
-
-// Cut rows into tiles of consecutive rows with at most `cap` entries and at
-// most kMaxTileRows rows; a longer row is a tile of its own.
-int build_tiles(damn_mat A, int32_t cap) {
-  if (A->d_tiles && A->tiles_cap == cap) return DAMN_OK;
-  std::vector<int32_t> starts;
-  try {
-    starts.reserve(size_t(A->nrows / 8 + 2));
-    const int32_t* rp = A->h_rowptr.data();
-    int32_t r = 0;
-    while (r < A->nrows) {
-      starts.push_back(r);
-      const int32_t first = r;
-      if (rp[r + 1] - rp[r] > cap) {
-        ++r;
-        continue;
-      }
-      while (r < A->nrows && r - first < kMaxTileRows && rp[r + 1] - rp[first] <= cap) ++r;
-    }
-    starts.push_back(A->nrows);
-  } catch (const std::bad_alloc&) {
-    return DAMN_ERR_ALLOC;
-  }
-  int32_t* d = nullptr;
-  if (hipMalloc(&d, sizeof(int32_t) * starts.size()) != hipSuccess) return DAMN_ERR_ALLOC;
-  if (hipMemcpy(d, starts.data(), sizeof(int32_t) * starts.size(), hipMemcpyHostToDevice) !=
-      hipSuccess) {
-    hipFree(d);
-    return DAMN_ERR_HIP;
-  }
-  if (A->d_tiles) hipFree(A->d_tiles);
-  A->d_tiles = d;
-  A->ntiles = int64_t(starts.size()) - 1;
-  A->tiles_cap = cap;
-  return DAMN_OK;
 }
 
 int create_common(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* rowptr,

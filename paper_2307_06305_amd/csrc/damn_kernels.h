@@ -32,6 +32,11 @@ struct SpmvArgs {
 
 // variant 0 = vector (lanes, unroll), 1 = stream (lanes = G, tiles in args)
 hipError_t launch_spmv(const SpmvArgs& a, int variant, int lanes, int unroll);
+// Stream variant with the conjugate-gradient epilogue: partial[t] = sum of
+// y_r * w_r over tile t (w = nullptr: w = y), skipped entirely when *done.
+// lanes in {1, 2, 4, 8, 16}; alpha != 0.
+hipError_t launch_spmv_dot(const SpmvArgs& a, int lanes, const void* w, double* partial,
+                           const int32_t* done);
 // float64 only; 1 <= nrhs <= 8
 hipError_t launch_spmm(const SpmvArgs& a, int lanes, int nrhs);
 hipError_t launch_stream_read(const void* src, int64_t bytes, double* sink, hipStream_t s);

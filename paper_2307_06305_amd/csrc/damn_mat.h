@@ -1,0 +1,33 @@
+// The device matrix handle, shared by the library's HIP translation units.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "damn.h"
+
+struct damn_cg_work;  // conjugate-gradient workspace, allocated on first use
+
+struct damn_mat_s {
+  int device = 0;
+  int32_t nrows = 0, ncols = 0;
+  int64_t nnz = 0;
+  int32_t format = DAMN_FORMAT_DA16;
+  int32_t dtype = DAMN_F64;
+  int32_t* d_rowptr = nullptr;
+  void* d_idx = nullptr;  // int16 offsets or int32 columns, padded
+  void* d_val = nullptr;  // float64 or float32 values, padded
+  std::vector<int32_t> h_rowptr;  // host copy, for building stream tiles
+  damn_config cfg{};
+  int32_t* d_tiles = nullptr;  // stream tiles: first row of each tile, plus nrows
+  int64_t ntiles = 0;
+  int32_t tiles_cap = 0;
+  damn_cg_work* cg = nullptr;
+};
+
+namespace damn {
+// Build (or reuse) the stream tiles of A for entry cap `cap`.
+int build_tiles(damn_mat A, int32_t cap);
+// Free the conjugate-gradient workspace of A, if any.
+void release_cg_work(damn_mat A);
+}  // namespace damn

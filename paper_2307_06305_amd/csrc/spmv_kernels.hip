@@ -119,12 +119,28 @@ __device__ __forceinline__ void copy_to_lds(T* __restrict__ dst, const T* __rest
 #endif
 }
 
-template <typename I, typename V, bool DA, int G>
+// Workgroup sum of one double per thread, in a fixed order (wave sums, then
+// the four wave results left to right); the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* scratch4) {
+  v = group_sum(v, 64);
+  if ((threadIdx.x & 63) == 0) scratch4[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (scratch4[0] + scratch4[1]) + (scratch4[2] + scratch4[3]);
+}
+
+// Optional epilogue for conjugate gradients (DOT): each workgroup also writes
+// partial[t] = sum over its rows of y_r * w_r in float64 (w = nullptr means
+// w = y), and every workgroup returns at once when *done is nonzero.
+template <typename I, typename V, bool DA, int G, bool DOT = false>
 __global__ __launch_bounds__(256) void spmv_stream(
     const int32_t* __restrict__ tile_row, const int32_t* __restrict__ rowptr,
     const I* __restrict__ idx, const V* __restrict__ val, const V* __restrict__ x,
-    V* __restrict__ y, V alpha, V beta, int32_t read_y, int32_t cap) {
+    V* __restrict__ y, V alpha, V beta, int32_t read_y, int32_t cap,
+    const V* __restrict__ w = nullptr, double* __restrict__ partial = nullptr,
+    const int32_t* __restrict__ done = nullptr) {
   extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ double red[4];
+  if (DOT && *done) return;
   V* val_s = reinterpret_cast<V*>(lds);
   I* idx_s = reinterpret_cast<I*>(lds + sizeof(V) * (cap + 16));
 
@@ -143,7 +159,9 @@ __global__ __launch_bounds__(256) void spmv_stream(
     __syncthreads();
     if (threadIdx.x == 0) {
       const V s = (part[0] + part[1]) + (part[2] + part[3]);
-      y[r0] = finish(s, alpha, beta, read_y != 0, y + r0);
+      const V yr = finish(s, alpha, beta, read_y != 0, y + r0);
+      y[r0] = yr;
+      if (DOT) partial[t] = double(yr) * double(w ? w[r0] : yr);
     }
     return;
   }
@@ -160,6 +178,7 @@ __global__ __launch_bounds__(256) void spmv_stream(
 
   // 2. G lanes per row
   const int lane = threadIdx.x % G;
+  double dot = 0.0;
   for (int32_t r = r0 + int32_t(threadIdx.x / G); r < r1; r += 256 / G) {
     const int32_t s = rowptr[r] - a0, e = rowptr[r + 1] - a0;
     const V* xs = DA ? x + r : x;
@@ -174,7 +193,15 @@ __global__ __launch_bounds__(256) void spmv_stream(
       if (k + u * G < e) acc[u] += val_s[k + u * G] * xs[idx_s[k + u * G]];
     V sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     if (G > 1) sum = group_sum(sum, G);
-    if (lane == 0) y[r] = finish(sum, alpha, beta, read_y != 0, y + r);
+    if (lane == 0) {
+      const V yr = finish(sum, alpha, beta, read_y != 0, y + r);
+      y[r] = yr;
+      if (DOT) dot += double(yr) * double(w ? w[r] : yr);
+    }
+  }
+  if (DOT) {
+    dot = block_sum(dot, red);
+    if (threadIdx.x == 0) partial[t] = dot;
   }
 }
 
@@ -306,6 +333,31 @@ hipError_t launch_stream_g(const SpmvArgs& a) {
   return hipGetLastError();
 }
 
+template <typename I, typename V, bool DA, int G>
+hipError_t launch_stream_dot_g(const SpmvArgs& a, const void* w, double* partial,
+                               const int32_t* done) {
+  if (a.ntiles == 0) return hipSuccess;
+  const size_t shmem = size_t(a.cap + 16) * (sizeof(I) + sizeof(V));
+  hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, true>), dim3(uint32_t(a.ntiles)), dim3(256),
+                     shmem, a.stream, a.tile_row, a.rowptr, static_cast<const I*>(a.idx),
+                     static_cast<const V*>(a.val), static_cast<const V*>(a.x),
+                     static_cast<V*>(a.y), V(a.alpha), V(a.beta), a.read_y, a.cap,
+                     static_cast<const V*>(w), partial, done);
+  return hipGetLastError();
+}
+
+template <typename I, typename V, bool DA>
+hipError_t launch_stream_dot(const SpmvArgs& a, int lanes, const void* w, double* partial,
+                             const int32_t* done) {
+  switch (lanes) {
+    case 1: return launch_stream_dot_g<I, V, DA, 1>(a, w, partial, done);
+    case 2: return launch_stream_dot_g<I, V, DA, 2>(a, w, partial, done);
+    case 4: return launch_stream_dot_g<I, V, DA, 4>(a, w, partial, done);
+    case 8: return launch_stream_dot_g<I, V, DA, 8>(a, w, partial, done);
+    default: return launch_stream_dot_g<I, V, DA, 16>(a, w, partial, done);
+  }
+}
+
 template <typename I, typename V, bool DA>
 hipError_t launch_stream(const SpmvArgs& a, int lanes) {
   switch (lanes) {
@@ -389,6 +441,15 @@ hipError_t launch_spmv(const SpmvArgs& a, int variant, int lanes, int unroll) {
                  : launch_vector<int16_t, double, true>(a, lanes, unroll);
   return a.f32 ? launch_vector<int32_t, float, false>(a, lanes, unroll)
                : launch_vector<int32_t, double, false>(a, lanes, unroll);
+}
+
+hipError_t launch_spmv_dot(const SpmvArgs& a, int lanes, const void* w, double* partial,
+                           const int32_t* done) {
+  if (a.da)
+    return a.f32 ? launch_stream_dot<int16_t, float, true>(a, lanes, w, partial, done)
+                 : launch_stream_dot<int16_t, double, true>(a, lanes, w, partial, done);
+  return a.f32 ? launch_stream_dot<int32_t, float, false>(a, lanes, w, partial, done)
+               : launch_stream_dot<int32_t, double, false>(a, lanes, w, partial, done);
 }
 
 hipError_t launch_spmm(const SpmvArgs& a, int lanes, int nrhs) {

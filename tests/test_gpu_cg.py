@@ -1,0 +1,136 @@
+"""GPU conjugate gradients (float64 and mixed precision) against the CPU
+oracle: the true residual of the GPU solution recomputed by the oracle, the
+solution against the oracle's float64 CG solution, and iteration counts."""
+
+import numpy as np
+import pytest
+
+import paper_2307_06305_amd as D
+from gpu_util import dev, host, torch_or_skip
+from oracle import cg as OC
+from oracle import spmv as OS
+from workloads import laplace_2d_5pt, poisson_3d_7pt, uniform_vector
+
+pytestmark = pytest.mark.gpu
+
+
+def _handles(A, fmt):
+    if fmt == "da":
+        e = D.encode(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, allow_rcm=False)
+        A64 = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], e["vals"], store=D.F64)
+        A32 = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], e["vals"], store=D.F32)
+    else:
+        A64 = D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, store=D.F64)
+        A32 = D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, store=D.F32)
+    return A64, A32
+
+
+def _true_rel_res(A, x, b):
+    r = b - OS.spmv_csr(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, x)
+    return np.linalg.norm(r) / np.linalg.norm(b)
+
+
+MATS = [laplace_2d_5pt(40), poisson_3d_7pt(14, 12, 16)]
+
+
+@pytest.mark.parametrize("fmt", ["da", "csr"])
+@pytest.mark.parametrize("A", MATS, ids=lambda A: A.name)
+def test_cg_fp64_matches_oracle(A, fmt):
+    torch_or_skip()
+    b = uniform_vector(A.nrows, 31)
+    A64, A32 = _handles(A, fmt)
+    xd = dev(np.zeros(A.nrows))
+    info = D.cg(A64, dev(b), xd, tol=1e-10, check_every=7)
+    x = host(xd)
+    ref = OC.cg_fp64(lambda v: OS.spmv_csr(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, v), b)
+    assert info["converged"] and ref["converged"]
+    # the library's own residual report agrees with the oracle's recomputation
+    rr = _true_rel_res(A, x, b)
+    assert rr <= 1.05e-10
+    assert abs(info["rel_res"] - rr) <= 1e-12
+    # same recurrence in a different summation order: iteration counts agree
+    assert abs(info["iters"] - ref["iters"]) <= 2
+    # solutions agree to the conditioning of the problem
+    Dm = OS.dense(A.nrows, A.ncols, A.rowptr, A.colids, A.vals)
+    kappa = np.linalg.cond(Dm)
+    assert np.linalg.norm(x - ref["x"]) <= 10 * kappa * 1e-10 * np.linalg.norm(ref["x"])
+    A64.destroy()
+    A32.destroy()
+
+
+@pytest.mark.parametrize("fmt", ["da", "csr"])
+@pytest.mark.parametrize("A", MATS, ids=lambda A: A.name)
+def test_cg_mixed_reaches_fp64_residual(A, fmt):
+    torch_or_skip()
+    b = uniform_vector(A.nrows, 32)
+    A64, A32 = _handles(A, fmt)
+    xd = dev(np.zeros(A.nrows))
+    info = D.cg(A64, dev(b), xd, A32=A32, tol=1e-10, inner_tol=1e-5, check_every=5)
+    x = host(xd)
+    assert info["converged"]
+    rr = _true_rel_res(A, x, b)
+    assert rr <= 1e-10
+    assert abs(info["rel_res"] - rr) <= 1e-12
+    assert 2 <= info["outer"] <= 4
+    # error against the oracle's float64 CG solution (reported; bounded by
+    # the conditioning)
+    ref = OC.cg_fp64(lambda v: OS.spmv_csr(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, v), b)
+    Dm = OS.dense(A.nrows, A.ncols, A.rowptr, A.colids, A.vals)
+    kappa = np.linalg.cond(Dm)
+    err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"])
+    print(f"{A.name} {fmt}: outer {info['outer']} inner {info['iters']} rel err vs fp64 {err:.2e}")
+    assert err <= 10 * kappa * 1e-10
+    # the oracle's own mixed scheme needs a similar number of inner iterations
+    v32 = A.vals.astype(np.float32)
+    om = OC.cg_mixed(
+        lambda v: OS.spmv_csr(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, v),
+        lambda v: OS.spmv_csr(A.nrows, A.ncols, A.rowptr, A.colids, v32, v).astype(np.float32),
+        b)
+    assert om["converged"] and om["outer"] == info["outer"]
+    assert abs(om["inner_iters"] - info["iters"]) <= 0.1 * om["inner_iters"] + 4
+    A64.destroy()
+    A32.destroy()
+
+
+def test_cg_iteration_limit_and_zero_rhs():
+    torch_or_skip()
+    A = laplace_2d_5pt(30)
+    A64, A32 = _handles(A, "da")
+    b = uniform_vector(A.nrows, 3)
+    info = D.cg(A64, dev(b), dev(np.zeros(A.nrows)), max_iter=5, check_every=2)
+    assert not info["converged"] and info["iters"] == 5
+    info = D.cg(A64, dev(np.zeros(A.nrows)), dev(np.ones(A.nrows)))
+    assert info["converged"] and info["iters"] == 0
+    A64.destroy()
+    A32.destroy()
+
+
+def test_cg_breakdown_on_indefinite_matrix():
+    torch_or_skip()
+    n = 64
+    rp = np.arange(n + 1, dtype=np.int32)
+    off = np.zeros(n, dtype=np.int16)
+    vals = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    A64 = D.Matrix.create(n, n, rp, off, vals)
+    b = np.zeros(n)
+    b[1] = 1.0  # p.Ap = -1 in the first step
+    with pytest.raises(D.DamnError) as ei:
+        D.cg(A64, dev(b), dev(np.zeros(n)))
+    assert ei.value.code == -8
+    A64.destroy()
+
+
+def test_cg_rejects_bad_arguments():
+    torch_or_skip()
+    A = laplace_2d_5pt(8)
+    A64, A32 = _handles(A, "da")
+    C64, _ = _handles(A, "csr")
+    b, x = dev(np.ones(64)), dev(np.zeros(64))
+    with pytest.raises(D.DamnError):
+        D.cg(A32, b, x)                  # float32 handle as the float64 matrix
+    with pytest.raises(D.DamnError):
+        D.cg(A64, b, x, A32=C64)         # formats differ / wrong dtype
+    with pytest.raises(D.DamnError):
+        D.cg(A64, b, x, tol=0.0)
+    for m in (A64, A32, C64):
+        m.destroy()

@@ -90,12 +90,29 @@ int damn_fit_check(int32_t nrows, int32_t ncols, const int32_t* rowptr,
 int damn_rcm(int32_t n, const int32_t* rowptr, const int32_t* colids,
              int32_t* perm);
 
+/* Bandwidth refinement of an ordering, for matrices whose RCM order still
+ * has w >= 32768 (the paper's RCM fell short on two matrices, Sec. 3).  A
+ * sweep gives each vertex of the pattern graph of A + A^T the key
+ * min + max of its neighbours' current positions (2 * its own position if
+ * it has none) and re-sorts the vertices by (key, current position).  Sweeps
+ * repeat until the order's bandwidth is below `limit` (32768 for 16-bit
+ * offsets), at most max_sweeps.
+ * In:  square int32 CSR of order n, perm[n] (new -> old) to start from.
+ * Out: perm[n] replaced by the first fitting order, or by the narrowest one
+ *      seen; *w_out its bandwidth.
+ * Errors: DAMN_ERR_NO_FIT (no fitting order; perm and *w_out still written),
+ *         DAMN_ERR_INVALID_ARG (perm not a permutation), DAMN_ERR_BAD_CSR,
+ *         DAMN_ERR_ALLOC. */
+int damn_refine_bandwidth(int32_t n, const int32_t* rowptr, const int32_t* colids,
+                          int32_t* perm, int32_t max_sweeps, int32_t limit, int32_t* w_out);
+
 /* CSR -> DA-CSR with 16-bit offsets (Sec. 2, Example 1).
  * If w < 32768 in the given order: rowptr and values are copied, and
  * off[i] = colids[i] - r_i, entry order unchanged; perm_out (if not NULL)
  * gets the identity and *permuted = 0.
  * Otherwise, if allow_rcm != 0 and the matrix is square: the RCM
- * permutation is applied as P A P^T (new row i = old row perm[i], column c
+ * permutation (refined by damn_refine_bandwidth with 32 sweeps when the RCM
+ * order alone does not fit) is applied as P A P^T (new row i = old row perm[i], column c
  * relabelled to inv[c]; within a row entries ordered by new column, equal
  * columns keep their old order), the fit is checked again and *permuted = 1.
  * Products with a permuted matrix are in permuted space: x_p[i] = x[perm[i]]

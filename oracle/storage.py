@@ -124,13 +124,15 @@ def encode(nrows, ncols, rowptr, colids, vals, allow_rcm=True):
     If the natural order fits (w < 2^15) the entries keep their order and
     values, and only the column indices are rewritten (Sec. 2).  Otherwise,
     when reordering is allowed and the matrix is square, the reverse
-    Cuthill-McKee permutation is applied first (Sec. 2, Example 2; Sec. 3)
-    and the fit is checked again.  Raises NoFit when no fitting form is found.
+    Cuthill-McKee permutation is applied first (Sec. 2, Example 2; Sec. 3),
+    refined by midpoint sweeps (rcm.midpoint_refine) when the RCM order alone
+    does not fit, and the fit is checked again.  Raises NoFit when no fitting
+    form is found.
 
     Returns a dict with rowptr, off (int16), vals, perm (new -> old; the
     identity if not permuted), permuted and w (bandwidth of the result).
     """
-    from .rcm import rcm
+    from .rcm import midpoint_refine, rcm
 
     w, lo, hi, fits = fit(nrows, ncols, rowptr, colids)
     if fits:
@@ -145,6 +147,9 @@ def encode(nrows, ncols, rowptr, colids, vals, allow_rcm=True):
     if not allow_rcm or nrows != ncols:
         raise NoFit(w)
     perm = rcm(nrows, rowptr, colids)
+    perm, w_perm, _ = midpoint_refine(nrows, rowptr, colids, perm)
+    if w_perm >= INT16_BANDWIDTH_LIMIT:
+        raise NoFit(w_perm)
     rp, cols, v = permute_symmetric(nrows, rowptr, colids, vals, perm)
     w2, _, _, fits2 = fit(nrows, ncols, rp, cols)
     if not fits2:

@@ -83,6 +83,21 @@ def rcm(n, rowptr, colids):
     return perm
 
 
+def refine_bandwidth(n, rowptr, colids, perm, max_sweeps=32, limit=2**15):
+    """Midpoint refinement of an ordering (host).  Returns (perm, w, fits)."""
+    c = _i32(colids)
+    rp = _csr_arrays(n, rowptr, c)
+    p = np.array(perm, dtype=np.int32, copy=True)
+    if p.shape != (n,):
+        raise DamnError(-1, "perm must have n entries")
+    w = C.c_int32()
+    st = lib.damn_refine_bandwidth(n, _ptr(rp, C.c_int32), _ptr(c, C.c_int32),
+                                   _ptr(p, C.c_int32), int(max_sweeps), int(limit), C.byref(w))
+    if st not in (0, -3):
+        raise DamnError(st, "refine_bandwidth")
+    return p, w.value, st == 0
+
+
 def encode(nrows, ncols, rowptr, colids, vals, allow_rcm=True):
     """CSR -> DA-CSR int16 (host).  Returns dict(rowptr, off, vals, perm,
     permuted, w); raises NoFit (with .w) when no fitting form exists."""

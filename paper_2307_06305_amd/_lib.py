@@ -49,6 +49,7 @@ _SIGS = {
     "damn_version": (C.c_char_p, []),
     "damn_fit_check": (C.c_int, [_i32, _i32, _pi32, _pi32, _pi32, _pi32, _pi32, _pi32]),
     "damn_rcm": (C.c_int, [_i32, _pi32, _pi32, _pi32]),
+    "damn_refine_bandwidth": (C.c_int, [_i32, _pi32, _pi32, _pi32, _i32, _i32, _pi32]),
     "damn_encode": (C.c_int, [_i32, _i32, _pi32, _pi32, _pf64, _i32, _pi32, _pi16, _pf64, _pi32,
                               _pi32, _pi32]),
     "damn_create": (C.c_int, [C.POINTER(_vp), _i32, _i32, _pi32, _pi16, _vp, _i32, _i32, _vp]),

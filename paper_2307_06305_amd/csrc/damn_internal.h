@@ -40,5 +40,8 @@ int check_csr(int32_t nrows, int32_t ncols, const int32_t* rowptr,
               const int32_t* colids);
 void bandwidth(int32_t nrows, const int32_t* rowptr, const int32_t* colids,
                int64_t* lo, int64_t* hi);
+int refine_bandwidth(int32_t n, const int32_t* rowptr, const int32_t* colids, int32_t* perm,
+                     int32_t max_sweeps, int64_t limit, int64_t* w_out);
+constexpr int32_t kRefineSweeps = 32;
 
 }  // namespace damn

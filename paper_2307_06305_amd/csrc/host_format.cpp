@@ -151,6 +151,18 @@ extern "C" int damn_encode(int32_t nrows, int32_t ncols, const int32_t* rowptr,
   }
   st = damn_rcm(nrows, rowptr, colids, perm.data());
   if (st != DAMN_OK) return st;
+  // the RCM order alone may stay too wide: refine it
+  int64_t wr = 0;
+  try {
+    st = refine_bandwidth(nrows, rowptr, colids, perm.data(), kRefineSweeps,
+                          kInt16BandwidthLimit, &wr);
+  } catch (const std::bad_alloc&) {
+    return DAMN_ERR_ALLOC;
+  }
+  if (st != DAMN_OK) {
+    *w_out = int32_t(wr);
+    return st;
+  }
   st = permute_symmetric(nrows, rowptr, colids, vals, perm.data(), rp2, c2, v2);
   if (st != DAMN_OK) return st;
   bandwidth(nrows, rp2.data(), c2.data(), &l, &h);

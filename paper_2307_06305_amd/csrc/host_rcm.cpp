@@ -11,6 +11,7 @@
 //              the whole order reversed (perm[new] = old)
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -117,10 +118,100 @@ LevelInfo levels_from(const Graph& g, int32_t root, std::vector<int32_t>& mark,
   return {depth, best};
 }
 
+// max |pos[u] - pos[v]| over graph edges
+int64_t graph_bandwidth(const Graph& g, const std::vector<int32_t>& pos) {
+  std::mutex m;
+  int64_t w = 0;
+  parallel_for(g.n, [&](int64_t b, int64_t e) {
+    int64_t local = 0;
+    for (int64_t v = b; v < e; ++v)
+      for (int64_t k = g.ptr[v]; k < g.ptr[v + 1]; ++k) {
+        const int64_t d = int64_t(pos[g.adj[k]]) - pos[v];
+        local = std::max(local, d < 0 ? -d : d);
+      }
+    std::lock_guard<std::mutex> l(m);
+    w = std::max(w, local);
+  }, 4096);
+  return w;
+}
+
 }  // namespace
+
+// Midpoint refinement sweeps (see damn_refine_bandwidth).  perm is replaced
+// by the first order with bandwidth < limit, or by the narrowest order seen.
+int refine_bandwidth(int32_t n, const int32_t* rowptr, const int32_t* colids, int32_t* perm,
+                     int32_t max_sweeps, int64_t limit, int64_t* w_out) {
+  Graph g;
+  build_graph(n, rowptr, colids, g);
+  std::vector<int32_t> pos(n), cur(perm, perm + n), best(perm, perm + n);
+  for (int32_t i = 0; i < n; ++i) pos[cur[i]] = i;
+  int64_t best_w = graph_bandwidth(g, pos);
+  if (best_w >= limit) {
+    std::vector<std::pair<int64_t, int32_t>> keyed(n);
+    for (int32_t sweep = 1; sweep <= max_sweeps; ++sweep) {
+      parallel_for(n, [&](int64_t b, int64_t e) {
+        for (int64_t v = b; v < e; ++v) {
+          int64_t key = 2 * int64_t(pos[v]);
+          if (g.ptr[v + 1] > g.ptr[v]) {
+            int32_t mn = pos[g.adj[g.ptr[v]]], mx = mn;
+            for (int64_t k = g.ptr[v] + 1; k < g.ptr[v + 1]; ++k) {
+              mn = std::min(mn, pos[g.adj[k]]);
+              mx = std::max(mx, pos[g.adj[k]]);
+            }
+            key = int64_t(mn) + mx;
+          }
+          // (key, current position) is unique per vertex
+          keyed[pos[v]] = {key, int32_t(v)};
+        }
+      }, 4096);
+      // keyed is indexed by current position, so sorting by key and then by
+      // index orders ties by current position
+      std::vector<int32_t> order(n);
+      for (int32_t i = 0; i < n; ++i) order[i] = i;
+      std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return keyed[a].first != keyed[b].first ? keyed[a].first < keyed[b].first : a < b;
+      });
+      for (int32_t i = 0; i < n; ++i) cur[i] = keyed[order[i]].second;
+      for (int32_t i = 0; i < n; ++i) pos[cur[i]] = i;
+      const int64_t w = graph_bandwidth(g, pos);
+      if (w < best_w) {
+        best_w = w;
+        best = cur;
+      }
+      if (w < limit) break;
+    }
+  }
+  std::copy(best.begin(), best.end(), perm);
+  *w_out = best_w;
+  return best_w < limit ? DAMN_OK : DAMN_ERR_NO_FIT;
+}
+
 }  // namespace damn
 
 using namespace damn;
+
+extern "C" int damn_refine_bandwidth(int32_t n, const int32_t* rowptr, const int32_t* colids,
+                                     int32_t* perm, int32_t max_sweeps, int32_t limit,
+                                     int32_t* w_out) {
+  if ((perm == nullptr && n > 0) || w_out == nullptr || max_sweeps < 0 || limit < 1)
+    return DAMN_ERR_INVALID_ARG;
+  int st = check_csr(n, n, rowptr, colids);
+  if (st != DAMN_OK) return st;
+  // perm must be a permutation of 0..n-1
+  std::vector<char> seen(n, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    if (perm[i] < 0 || perm[i] >= n || seen[perm[i]]) return DAMN_ERR_INVALID_ARG;
+    seen[perm[i]] = 1;
+  }
+  int64_t w = 0;
+  try {
+    st = refine_bandwidth(n, rowptr, colids, perm, max_sweeps, limit, &w);
+  } catch (const std::bad_alloc&) {
+    return DAMN_ERR_ALLOC;
+  }
+  *w_out = int32_t(w);
+  return st;
+}
 
 extern "C" int damn_rcm(int32_t n, const int32_t* rowptr, const int32_t* colids,
                         int32_t* perm) {

@@ -164,3 +164,56 @@ def test_null_pointer_status():
 def test_rcm_full_size_banded_scrambled_matches_oracle():
     Q = config_matrix(2, scrambled=True)
     assert np.array_equal(D.rcm(Q.nrows, Q.rowptr, Q.colids), OR.rcm(Q.nrows, Q.rowptr, Q.colids))
+
+
+def test_refine_by_hand_through_the_library():
+    # path 0-1-2-3 ordered [1, 0, 3, 2] -> one sweep gives [0, 2, 1, 3], w 2
+    rp = [0, 1, 3, 5, 6]
+    c = [1, 0, 2, 1, 3, 2]
+    perm, w, fits = D.refine_bandwidth(4, rp, c, [1, 0, 3, 2], limit=3)
+    assert perm.tolist() == [0, 2, 1, 3] and w == 2 and fits
+
+
+@pytest.mark.parametrize("limit", [2600, 3000, 100000])
+def test_refine_matches_oracle_bit_exact(limit):
+    B = scramble_symmetric(random_banded(60000, 9, half_band=2000), 3)
+    n = B.nrows
+    start = OR.rcm(n, B.rowptr, B.colids)
+    p_lib, w_lib, fits = D.refine_bandwidth(n, B.rowptr, B.colids, start, limit=limit)
+    p_or, w_or, _ = OR.midpoint_refine(n, B.rowptr, B.colids, start, limit=limit)
+    assert np.array_equal(p_lib, p_or) and w_lib == w_or
+    assert fits == (w_or < limit)
+
+
+def test_refine_rejects_non_permutation():
+    with pytest.raises(D.DamnError) as ei:
+        D.refine_bandwidth(3, [0, 1, 2, 3], [0, 1, 2], [0, 0, 1])
+    assert ei.value.code == -1
+
+
+def test_encode_refined_banded_matches_oracle_bit_exact():
+    # a scrambled random band of half-width 20000: RCM alone comes back too
+    # wide for int16, the refinement sweeps make it fit
+    A = config_matrix(2, scrambled=True, scale=0.05)
+    n = A.nrows
+    assert D.fit_check(n, n, A.rowptr, A.colids)[0] > 100000
+    rcm_w = OS.fit(n, n, *OS.permute_symmetric(n, A.rowptr, A.colids, A.vals,
+                                              OR.rcm(n, A.rowptr, A.colids))[:2])[0]
+    assert rcm_w >= 32768
+    e = D.encode(n, n, A.rowptr, A.colids, A.vals, allow_rcm=True)
+    o = OS.encode(n, n, A.rowptr, A.colids, A.vals, allow_rcm=True)
+    assert e["permuted"] and e["w"] == o["w"] and e["w"] < 32768
+    for k in ("rowptr", "off", "perm"):
+        assert np.array_equal(e[k], o[k]), k
+    assert np.array_equal(e["vals"].view(np.uint64), o["vals"].view(np.uint64))
+
+
+@pytest.mark.slow
+def test_encode_full_size_banded_scrambled_matches_oracle():
+    Q = config_matrix(2, scrambled=True)
+    n = Q.nrows
+    e = D.encode(n, n, Q.rowptr, Q.colids, Q.vals, allow_rcm=True)
+    o = OS.encode(n, n, Q.rowptr, Q.colids, Q.vals, allow_rcm=True)
+    assert e["w"] == o["w"] < 32768
+    for k in ("rowptr", "off", "perm"):
+        assert np.array_equal(e[k], o[k]), k

@@ -201,3 +201,35 @@ def test_perm_is_permutation_with_isolated_and_empty():
     A = random_csr(300, 300, 2, mean_len=1.0, empty_frac=0.5)
     perm = R.rcm(300, A.rowptr, A.colids)
     assert np.array_equal(np.sort(perm), np.arange(300))
+
+
+def test_midpoint_refine_by_hand():
+    # path 0-1-2-3 ordered [1, 0, 3, 2]: positions 1:0 0:1 3:2 2:3, edge 1-2
+    # spans 3.  Keys (min + max neighbour position): v0: 0+0 = 0, v1: 1+3 = 4,
+    # v2: 0+2 = 2, v3: 3+3 = 6 -> order [0, 2, 1, 3] with bandwidth 2 < 3.
+    rp, c = _csr_from_edges(4, [(0, 1), (1, 2), (2, 3)])
+    perm, w, sweeps = R.midpoint_refine(4, rp, c, [1, 0, 3, 2], limit=3)
+    assert perm.tolist() == [0, 2, 1, 3] and w == 2 and sweeps == 1
+
+
+def test_midpoint_refine_keeps_narrowest_when_nothing_fits():
+    # path 0-1-2-3-4 ordered [0, 2, 4, 1, 3] (bandwidth 3): one sweep gives
+    # [1, 3, 0, 2, 4] (bandwidth 3), the next returns to the start; with
+    # limit 3 nothing fits and the earliest narrowest order is the input.
+    rp, c = _csr_from_edges(5, [(0, 1), (1, 2), (2, 3), (3, 4)])
+    perm, w, sweeps = R.midpoint_refine(5, rp, c, [0, 2, 4, 1, 3], limit=3, max_sweeps=4)
+    assert perm.tolist() == [0, 2, 4, 1, 3] and w == 3 and sweeps == 4
+
+
+def test_midpoint_refine_brings_scrambled_band_into_range():
+    # RCM leaves a random band at about twice its half-width; refinement
+    # brings it below 1.5 half-widths
+    A = random_banded(60000, 9, half_band=2000)
+    Q = scramble_symmetric(A, 3)
+    n = Q.nrows
+    perm = R.rcm(n, Q.rowptr, Q.colids)
+    assert _bandwidth_after(n, Q.rowptr, Q.colids, perm) > 3000
+    p2, w, sweeps = R.midpoint_refine(n, Q.rowptr, Q.colids, perm, limit=3000)
+    assert w < 3000 and 1 <= sweeps <= 32
+    assert w == _bandwidth_after(n, Q.rowptr, Q.colids, p2)
+    assert np.array_equal(np.sort(p2), np.arange(n))

@@ -74,6 +74,118 @@ def cpu_baseline(A, e, x, budget_s=12.0):
     return dt, reps
 
 
+def spmv_pair(D, M, Cm, n, ncols, nnz, xd, tune_reps):
+    """Autotune and time a DA handle M and a CSR handle Cm on the same x."""
+    import torch
+
+    from paper_2307_06305_amd.tuning import autotune, config_name
+
+    y = torch.zeros(n, dtype=torch.float64, device=xd.device)
+    out = {}
+    for name, mat, iidx in (("da", M, 2), ("csr", Cm, 4)):
+        if mat is None:
+            continue
+        best, _ = autotune(mat, xd, y, reps=tune_reps)
+        t = epochs(lambda: mat.apply(xd, y), 30)
+        T = model_bytes(n, ncols, nnz, iidx)
+        out[name] = {"us": round(t * 1e6, 2), "gbs": round(T / t / 1e9, 1),
+                     "pct_hbm_peak": round(100 * T / t / 1e9 / HBM_PEAK_GBS, 2),
+                     "launch": config_name(best)}
+    if "da" in out and "csr" in out:
+        out["speedup"] = round(out["csr"]["us"] / out["da"]["us"], 4)
+        out["predicted_speedup"] = round(model_bytes(n, ncols, nnz, 4) / model_bytes(n, ncols, nnz, 2), 4)
+    return out
+
+
+def bench_banded(D, args):
+    """Random banded n = 4M (lognormal rows, half-width 20000): DA vs CSR in
+    natural order; the scrambled copy: CSR as scrambled, then host reordering
+    (RCM + refinement) and DA vs CSR in the new order."""
+    import numpy as np
+    import torch
+
+    from workloads import config_matrix, config_vector
+
+    dev = torch.device("cuda:0")
+    out = {}
+    A = config_matrix(2)
+    e = D.encode(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, allow_rcm=False)
+    x = torch.from_numpy(config_vector(2, A.ncols)).to(dev)
+    M = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], e["vals"])
+    Cm = D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals)
+    out["natural"] = {"n": A.nrows, "nnz": A.nnz, "bandwidth": e["w"],
+                      **spmv_pair(D, M, Cm, A.nrows, A.ncols, A.nnz, x, args.tune_reps)}
+    M.destroy()
+    Cm.destroy()
+    del A, e
+    log(f"banded natural: {out['natural']}")
+    Q = config_matrix(2, scrambled=True)
+    w_scr = D.fit_check(Q.nrows, Q.ncols, Q.rowptr, Q.colids)[0]
+    Cq = D.Matrix.csr_create(Q.nrows, Q.ncols, Q.rowptr, Q.colids, Q.vals)
+    scr = spmv_pair(D, None, Cq, Q.nrows, Q.ncols, Q.nnz, x, args.tune_reps)
+    Cq.destroy()
+    t0 = time.time()
+    e = D.encode(Q.nrows, Q.ncols, Q.rowptr, Q.colids, Q.vals, allow_rcm=True)
+    t_enc = time.time() - t0
+    # the reordered matrix in CSR form too, for the iso-order comparison
+    cols = (np.repeat(np.arange(Q.nrows, dtype=np.int64), np.diff(e["rowptr"]))
+            + e["off"].astype(np.int64)).astype(np.int32)
+    M = D.Matrix.create(Q.nrows, Q.ncols, e["rowptr"], e["off"], e["vals"])
+    Cr = D.Matrix.csr_create(Q.nrows, Q.ncols, e["rowptr"], cols, e["vals"])
+    out["scrambled"] = {"bandwidth_scrambled": w_scr, "bandwidth_reordered": e["w"],
+                        "reorder_encode_s": round(t_enc, 2), "csr_scrambled_order": scr["csr"],
+                        **spmv_pair(D, M, Cr, Q.nrows, Q.ncols, Q.nnz, x, args.tune_reps)}
+    M.destroy()
+    Cr.destroy()
+    log(f"banded scrambled: {out['scrambled']}")
+    return out
+
+
+def bench_cg(D, args):
+    """Time to 1e-10 relative residual: float64 CG against mixed-precision
+    iterative refinement (float32 DA-CSR inner solves), 7-point Poisson on a
+    128 x 128 x 1024 box (n 16,777,216), b uniform on [-1, 1], x0 = 0."""
+    import torch
+
+    from workloads import config_matrix, config_vector
+
+    dev = torch.device("cuda:0")
+    A = config_matrix(3)
+    e = D.encode(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, allow_rcm=False)
+    A64 = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], e["vals"], store=D.F64)
+    A32 = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], e["vals"], store=D.F32)
+    b = torch.from_numpy(config_vector(3, A.nrows)).to(dev)
+    x64 = torch.zeros_like(b)
+    xm = torch.zeros_like(b)
+    from paper_2307_06305_amd.tuning import STREAM, autotune, candidates, config_name
+    stream_cfgs = [c for c in candidates() if c[0] == STREAM and c[1] <= 16]
+    best64, _ = autotune(A64, b, x64, configs=stream_cfgs, reps=args.tune_reps)
+    b32 = b.float()
+    y32 = torch.zeros_like(b32)
+    best32, _ = autotune(A32, b32, y32, configs=stream_cfgs, reps=args.tune_reps)
+    del b32, y32
+    res = {"workload": "poisson3d_7pt_128x128x1024", "n": A.nrows, "nnz": A.nnz,
+           "bandwidth": e["w"], "tol": 1e-10, "launch_f64": config_name(best64),
+           "launch_f32": config_name(best32)}
+    for name, a32, xv in (("fp64", None, x64), ("mixed", A32, xm)):
+        best = None
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = D.cg(A64, b, xv, A32=a32, tol=1e-10, inner_tol=1e-5, max_iter=20000,
+                        check_every=32)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        res[name] = {"s": round(best, 4), **info}
+        log(f"cg {name}: {res[name]}")
+    res["speedup_mixed"] = round(res["fp64"]["s"] / res["mixed"]["s"], 3)
+    res["mixed_vs_fp64_rel_err"] = float(((xm - x64).norm() / x64.norm()).item())
+    A64.destroy()
+    A32.destroy()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +194,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tune-reps", type=int, default=10)
     ap.add_argument("--dump", default=None, help="write the autotuner's timing table here (JSON)")
+    ap.add_argument("--skip-banded", action="store_true", help="skip the random banded workload")
+    ap.add_argument("--skip-cg", action="store_true", help="skip the conjugate-gradient solves")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
@@ -197,6 +311,11 @@ def main():
         "max_abs_diff_da_vs_csr": diff,
         "paper_cpu_context": {"uplift_st": 0.11, "uplift_mt": 0.175, "predicted": 0.20},
     }
+
+    if not args.skip_banded:
+        res["banded"] = bench_banded(D, args)
+    if not args.skip_cg:
+        res["cg"] = bench_cg(D, args)
 
     if not args.no_cpu:
         t_cpu, reps = cpu_baseline(A, e, x)

@@ -243,8 +243,9 @@ typedef struct {
  * matrix with float32 values (same format and shape).  Each outer step forms
  * r = b - A64 x and ||r|| in float64; if not yet converged it runs CG on
  * A32 d = r/||r|| with float32 vectors, float32-accumulated products with
- * A32 and float64-accumulated dot products, to inner_tol, then x += ||r|| d.
- * b, x: device float64 vectors of n entries (x is overwritten; on
+ * A32 and float64-accumulated dot products, to the relative residual
+ * min(1/2, max(inner_tol, tol ||b|| / (2 ||r||))), then x += ||r|| d.
+ * b, x: device float64 vectors of n entries, 16-byte aligned (x is overwritten; on
  * DAMN_ERR_NOT_CONVERGED / DAMN_ERR_BREAKDOWN it holds the last iterate).
  * The call synchronises `stream` (it reads the stop flag every check_every
  * iterations).  Device workspace (about 7 vectors) is kept with A64.

@@ -12,9 +12,12 @@ cg_mixed -- iterative refinement: the outer loop keeps x, b and the residual
            r = b - A x in float64 (float64 matrix); each correction solves
            A d = r approximately with CG on the float32 matrix, the Krylov
            vectors held in float32 and dot products accumulated in float64,
-           to a relative residual of inner_tol.  The right-hand side of the
-           inner solve is r scaled to unit norm (and the correction scaled
-           back), so small late residuals stay in float32 range.
+           to a relative residual of max(inner_tol, tol*||b|| / (2 ||r||)):
+           a step never solves further than the outer target needs, so the
+           last step stops as soon as the outer residual will meet tol.  The
+           right-hand side of the inner solve is r scaled to unit norm (and
+           the correction scaled back), so small late residuals stay in
+           float32 range.
 
 `matvec64(v)` and `matvec32(v)` are caller-supplied products (the oracle's
 spmv on the float64 values and on the float32-rounded values).
@@ -88,7 +91,8 @@ def cg_mixed(matvec64, matvec32, b, tol=1e-10, inner_tol=1e-5, max_outer=50, max
     converged = rnorm <= tol * bnorm
     while not converged and outer < max_outer:
         rhs = (r / rnorm).astype(np.float32)
-        d, k = _inner_cg32(matvec32, rhs, inner_tol, max_inner)
+        target = min(0.5, max(inner_tol, 0.5 * tol * bnorm / rnorm))
+        d, k = _inner_cg32(matvec32, rhs, target, max_inner)
         inner_total += k
         x += rnorm * d.astype(np.float64)
         r = b - matvec64(x)

@@ -39,11 +39,38 @@ constexpr int kFinThreads = 1024;
 
 enum Op { kStart = 0, kAlpha = 1, kBeta = 2, kNorm = 3 };
 
-// Contiguous slice [s, e) of [0, n) for this workgroup, in multiples of 256.
-__device__ __forceinline__ void slice(int64_t n, int64_t* s, int64_t* e) {
-  const int64_t per = (((n + gridDim.x - 1) / gridDim.x) + 255) & ~int64_t(255);
+// Contiguous slice [s, e) of [0, n) for this workgroup; slice starts are
+// multiples of `align` elements.
+__device__ __forceinline__ void slice(int64_t n, int64_t align, int64_t* s, int64_t* e) {
+  const int64_t per = (((n + gridDim.x - 1) / gridDim.x) + align - 1) / align * align;
   *s = int64_t(blockIdx.x) * per;
   *e = *s + per < n ? *s + per : n;
+}
+
+// 16 bytes of V: 2 doubles or 4 floats, loaded and stored as one access.
+template <typename V>
+struct Pack {
+  static constexpr int kN = 16 / int(sizeof(V));
+  typedef V vec __attribute__((ext_vector_type(kN)));
+  static __device__ __forceinline__ vec load(const V* p) {
+    return *reinterpret_cast<const vec*>(p);
+  }
+  static __device__ __forceinline__ void store(V* p, vec v) { *reinterpret_cast<vec*>(p) = v; }
+};
+
+// Visit [s, e) of a slice in 16-byte packs: pack(base) for a whole pack
+// starting at element base, tail(i) for the elements after the last whole
+// pack (only in the last slice).
+template <typename V, typename FP, typename FT>
+__device__ __forceinline__ void for_packs(int64_t s, int64_t e, FP pack, FT tail) {
+  constexpr int kP = Pack<V>::kN;
+  for (int64_t base = s + int64_t(threadIdx.x) * kP; base < e; base += 256 * kP) {
+    if (base + kP <= e) {
+      pack(base);
+    } else {
+      for (int64_t i = base; i < e; ++i) tail(i);
+    }
+  }
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -66,15 +93,22 @@ __global__ __launch_bounds__(256) void init64(int64_t n, const double* __restric
                                               double* __restrict__ p,
                                               double* __restrict__ partial) {
   int64_t s, e;
-  slice(n, &s, &e);
+  slice(n, 512, &s, &e);
   double acc = 0.0;
-  for (int64_t i = s + threadIdx.x; i < e; i += 256) {
-    const double v = b[i];
-    x[i] = 0.0;
-    r[i] = v;
-    if (p) p[i] = v;
-    acc += v * v;
-  }
+  typedef Pack<double> P;
+  for_packs<double>(s, e, [&](int64_t base) {
+      const P::vec v = P::load(b + base);
+      P::store(x + base, P::vec(0.0));
+      P::store(r + base, v);
+      if (p) P::store(p + base, v);
+      acc += v.x * v.x + v.y * v.y;
+    }, [&](int64_t i) {
+      const double v = b[i];
+      x[i] = 0.0;
+      r[i] = v;
+      if (p) p[i] = v;
+      acc += v * v;
+    });
   acc = sum256(acc);
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
@@ -142,14 +176,26 @@ __global__ __launch_bounds__(256) void update_xr(int64_t n, V* __restrict__ x, V
   if (sc->done) return;
   const double a = sc->alpha;
   int64_t s, e;
-  slice(n, &s, &e);
+  slice(n, 1024, &s, &e);
   double acc = 0.0;
-  for (int64_t i = s + threadIdx.x; i < e; i += 256) {
-    x[i] = V(double(x[i]) + a * double(p[i]));
-    const V rn = V(double(r[i]) - a * double(q[i]));
-    r[i] = rn;
-    acc += double(rn) * double(rn);
-  }
+  typedef Pack<V> P;
+  for_packs<V>(s, e, [&](int64_t base) {
+      typename P::vec xv = P::load(x + base), rv = P::load(r + base);
+      const typename P::vec pv = P::load(p + base), qv = P::load(q + base);
+#pragma unroll
+      for (int k = 0; k < P::kN; ++k) {
+        xv[k] = V(double(xv[k]) + a * double(pv[k]));
+        rv[k] = V(double(rv[k]) - a * double(qv[k]));
+        acc += double(rv[k]) * double(rv[k]);
+      }
+      P::store(x + base, xv);
+      P::store(r + base, rv);
+    }, [&](int64_t i) {
+      x[i] = V(double(x[i]) + a * double(p[i]));
+      const V rn = V(double(r[i]) - a * double(q[i]));
+      r[i] = rn;
+      acc += double(rn) * double(rn);
+    });
   acc = sum256(acc);
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
@@ -162,8 +208,15 @@ __global__ __launch_bounds__(256) void update_p(int64_t n, V* __restrict__ p,
   if (sc->done) return;
   const double bt = sc->beta;
   int64_t s, e;
-  slice(n, &s, &e);
-  for (int64_t i = s + threadIdx.x; i < e; i += 256) p[i] = V(double(r[i]) + bt * double(p[i]));
+  slice(n, 1024, &s, &e);
+  typedef Pack<V> P;
+  for_packs<V>(s, e, [&](int64_t base) {
+      typename P::vec pv = P::load(p + base);
+      const typename P::vec rv = P::load(r + base);
+#pragma unroll
+      for (int k = 0; k < P::kN; ++k) pv[k] = V(double(rv[k]) + bt * double(pv[k]));
+      P::store(p + base, pv);
+    }, [&](int64_t i) { p[i] = V(double(r[i]) + bt * double(p[i])); });
 }
 
 // Inner solve start: rh = float(r / ||r||), d = 0, p = rh; partial = sum rh^2
@@ -174,7 +227,7 @@ __global__ __launch_bounds__(256) void mixed_start(int64_t n, const double* __re
                                                    double* __restrict__ partial) {
   const double inv = 1.0 / sqrt(outer->rho);
   int64_t s, e;
-  slice(n, &s, &e);
+  slice(n, 256, &s, &e);
   double acc = 0.0;
   for (int64_t i = s + threadIdx.x; i < e; i += 256) {
     const float v = float(r[i] * inv);
@@ -193,7 +246,7 @@ __global__ __launch_bounds__(256) void mixed_correct(int64_t n, double* __restri
                                                      const Scal* __restrict__ outer) {
   const double scale = sqrt(outer->rho);
   int64_t s, e;
-  slice(n, &s, &e);
+  slice(n, 256, &s, &e);
   for (int64_t i = s + threadIdx.x; i < e; i += 256) x[i] += scale * double(d[i]);
 }
 
@@ -354,6 +407,9 @@ extern "C" int damn_cg(damn_mat A64, damn_mat A32, const double* b, double* x,
   if (A64 == nullptr || opts == nullptr || info == nullptr) return DAMN_ERR_INVALID_ARG;
   if (A64->nrows != A64->ncols || A64->dtype != DAMN_F64) return DAMN_ERR_INVALID_ARG;
   if (A64->nrows > 0 && (b == nullptr || x == nullptr)) return DAMN_ERR_INVALID_ARG;
+  // the vector kernels move 16-byte packs
+  if ((reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(x)) & 15)
+    return DAMN_ERR_INVALID_ARG;
   if (A32 && (A32->nrows != A64->nrows || A32->ncols != A64->ncols ||
               A32->dtype != DAMN_F32 || A32->format != A64->format))
     return DAMN_ERR_INVALID_ARG;
@@ -412,7 +468,6 @@ extern "C" int damn_cg(damn_mat A64, damn_mat A32, const double* b, double* x,
   hipLaunchKernelGGL(cgk::finalize, dim3(1), dim3(cgk::kFinThreads), 0, s, w->partial,
                      int32_t(cgk::kVecBlocks), w->sc + 1, int32_t(cgk::kStart), tol2);
   DAMN_HIP_TRY(hipGetLastError());
-  const double inner2 = opts->inner_tol * opts->inner_tol;
   int32_t total_inner = 0;
   int32_t outer = 0;
   bool breakdown = false;
@@ -425,13 +480,17 @@ extern "C" int damn_cg(damn_mat A64, damn_mat A32, const double* b, double* x,
       break;
     }
     if (outer >= opts->max_outer) break;
-    // inner CG on A32 d = r / ||r||
+    // inner CG on A32 d = r / ||r||, to the relative residual the outer
+    // target still needs (never below inner_tol, never above 1/2)
+    double target = 0.5 * opts->tol * std::sqrt(o.b2 / o.rho);
+    if (target < opts->inner_tol) target = opts->inner_tol;
+    if (target > 0.5) target = 0.5;
     Scal fresh = init;
     DAMN_HIP_TRY(hipMemcpyAsync(w->sc, &fresh, sizeof(Scal), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(cgk::mixed_start, dim3(cgk::kVecBlocks), dim3(256), 0, s, n, w->r,
                        w->sc + 1, w->rh, w->d, w->p32, w->partial);
     hipLaunchKernelGGL(cgk::finalize, dim3(1), dim3(cgk::kFinThreads), 0, s, w->partial,
-                       int32_t(cgk::kVecBlocks), w->sc, int32_t(cgk::kStart), inner2);
+                       int32_t(cgk::kVecBlocks), w->sc, int32_t(cgk::kStart), target * target);
     DAMN_HIP_TRY(hipGetLastError());
     st = iterate<float>(A32, w, w->d, w->rh, w->p32, w->q32, opts->check_every, s);
     if (st != DAMN_OK) return st;

@@ -186,6 +186,77 @@ def bench_cg(D, args):
     return res
 
 
+def bench_batch(D, args):
+    """512 DA-CSR matrices (n log-uniform on [1e3, 2e5]; 2D 5-point, 3D
+    7-point, 3D 27-point and random banded; 1-8 right-hand sides): one
+    persistent graph-captured launch against 512 separately tuned launches."""
+    import numpy as np
+    import torch
+
+    from workloads.matrices import batch_matrix, batch_member
+
+    dev = torch.device("cuda:0")
+    count = args.batch_count
+    mats, Xs, Ys, lanes_best = [], [], [], []
+    total_nnz = total_rows = 0
+    t0 = time.time()
+    for i in range(count):
+        d = batch_member(1004, i)
+        A = batch_matrix(d)
+        e = D.encode(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, allow_rcm=False)
+        M = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], e["vals"])
+        k = d["nrhs"]
+        g = torch.Generator(device="cpu").manual_seed(7000 + i)
+        Xs.append((torch.rand(A.ncols, k, generator=g, dtype=torch.float64) * 2 - 1).to(dev))
+        Ys.append(torch.zeros(A.nrows, k, dtype=torch.float64, device=dev))
+        mats.append(M)
+        total_nnz += A.nnz
+        total_rows += A.nrows
+    log(f"batch: {count} matrices, {total_rows} rows, {total_nnz} entries "
+        f"({time.time() - t0:.1f}s to build)")
+    # separate launches: tune each matrix's SpMM lanes
+    for M, X, Y in zip(mats, Xs, Ys):
+        best = None
+        for l in (1, 2, 4, 8, 16, 32):
+            M.set_config(D.VAR_VECTOR, l, 1, 2048)
+            t = time_launches(lambda: M.spmm(X, Y), 3)
+            if best is None or t < best[0]:
+                best = (t, l)
+        lanes_best.append(best[1])
+    for M, l in zip(mats, lanes_best):
+        M.set_config(D.VAR_VECTOR, l, 1, 2048)
+
+    def separate():
+        for M, X, Y in zip(mats, Xs, Ys):
+            M.spmm(X, Y)
+
+    t_sep = epochs(separate, 3, 3)
+    # one persistent launch; each matrix reduces rows with the default lane
+    # count of the stream variant for its mean row length
+    for M in mats:
+        mean = M.nnz / max(M.nrows, 1)
+        g = 1 if mean < 4 else 2
+        while g < 16 and g * 16 < mean:
+            g *= 2
+        M.set_config(D.VAR_STREAM, g, 1, 2048)
+    B = D.Batch(mats, Xs, Ys, 1.0, 0.0, workgroups=args.batch_workgroups)
+    info = B.info()
+    t_graph = epochs(lambda: B.run(use_graph=True), 10, 5)
+    t_direct = epochs(lambda: B.run(use_graph=False), 10, 5)
+    T = info["model_bytes"]
+    res = {"matrices": count, "rows": total_rows, "nnz": total_nnz, "tiles": info["ntiles"],
+           "workgroups": info["workgroups"], "model_bytes": T,
+           "graph_us": round(t_graph * 1e6, 1), "graph_gbs": round(T / t_graph / 1e9, 1),
+           "direct_us": round(t_direct * 1e6, 1),
+           "separate_us": round(t_sep * 1e6, 1), "separate_gbs": round(T / t_sep / 1e9, 1),
+           "speedup_vs_separate": round(t_sep / t_graph, 3)}
+    log(f"batch: {res}")
+    B.destroy()
+    for M in mats:
+        M.destroy()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +267,9 @@ def main():
     ap.add_argument("--dump", default=None, help="write the autotuner's timing table here (JSON)")
     ap.add_argument("--skip-banded", action="store_true", help="skip the random banded workload")
     ap.add_argument("--skip-cg", action="store_true", help="skip the conjugate-gradient solves")
+    ap.add_argument("--skip-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-workgroups", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
@@ -316,6 +390,8 @@ def main():
         res["banded"] = bench_banded(D, args)
     if not args.skip_cg:
         res["cg"] = bench_cg(D, args)
+    if not args.skip_batch:
+        res["batch"] = bench_batch(D, args)
 
     if not args.no_cpu:
         t_cpu, reps = cpu_baseline(A, e, x)

@@ -255,6 +255,39 @@ int damn_cg(damn_mat A64, damn_mat A32, const double* b, double* x,
             const damn_cg_opts* opts, damn_cg_info* info, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Batched products: Y_i <- alpha*A_i*X_i + beta*Y_i for many DA-CSR
+ * matrices (the product of Sec. 4, repeated) in one persistent launch.
+ * --------------------------------------------------------------------- */
+
+typedef struct damn_batch_s* damn_batch;
+
+/* Prepare a batch over `count` float64 DA-CSR handles mats[i] with nrhs[i]
+ * right-hand sides (1..8).  X[i] (ncols_i x nrhs[i]) and Y[i] (nrows_i x
+ * nrhs[i]) are device pointers, row-major like damn_spmm; the batch keeps
+ * the pointers (not the data) and the handles' device arrays, which must
+ * outlive it.  Rows are cut into tiles of at most max(2048, longest row)
+ * entries (at most 4096) and the tile list is split into `workgroups`
+ * contiguous ranges of about equal modelled bytes (0: 1024 workgroups).
+ * The launch is captured once into a HIP graph.
+ * Errors: DAMN_ERR_INVALID_ARG (null, non-DA or non-float64 handle),
+ *         DAMN_ERR_UNSUPPORTED (nrhs outside 1..8, a row longer than 4096
+ *         entries), DAMN_ERR_ALLOC, DAMN_ERR_HIP. */
+int damn_batch_create(damn_batch* out, int32_t count, const damn_mat* mats,
+                      const int32_t* nrhs, const double* const* X, double* const* Y,
+                      double alpha, double beta, int32_t workgroups, void* stream);
+
+/* Run the batch on `stream`: use_graph != 0 replays the captured graph,
+ * otherwise the same kernel is launched directly.  Asynchronous. */
+int damn_batch_run(damn_batch B, int32_t use_graph, void* stream);
+
+/* Tiles, workgroups and modelled bytes of one run (matrices once, row
+ * pointers, X once, Y written and, if beta != 0, read). */
+int damn_batch_info(damn_batch B, int64_t* ntiles, int32_t* workgroups, double* model_bytes);
+
+/* Release a batch (waits for the device). */
+int damn_batch_destroy(damn_batch B);
+
+/* ------------------------------------------------------------------------
  * Measurement helpers.
  * --------------------------------------------------------------------- */
 

@@ -287,6 +287,56 @@ def cg(A64, b, x, A32=None, tol=1e-10, inner_tol=1e-5, max_iter=20000, max_outer
             "rel_res": info.rel_res}
 
 
+class Batch:
+    """Many DA-CSR products in one persistent, graph-captured launch.
+    mats: float64 DA-CSR Matrix objects; Xs/Ys: float64 device tensors of
+    shape (ncols, nrhs) / (nrows, nrhs); the tensors and matrices must
+    outlive the batch."""
+
+    def __init__(self, mats, Xs, Ys, alpha=1.0, beta=0.0, workgroups=0, stream=None):
+        import torch
+
+        count = len(mats)
+        if len(Xs) != count or len(Ys) != count:
+            raise ValueError("one X and one Y per matrix")
+        nrhs = np.array([int(X.shape[1]) for X in Xs], dtype=np.int32)
+        hs = (C.c_void_p * max(count, 1))(*[m.handle for m in mats])
+        xp = (C.c_void_p * max(count, 1))()
+        yp = (C.c_void_p * max(count, 1))()
+        for i, (m, X, Y) in enumerate(zip(mats, Xs, Ys)):
+            if X.dim() != 2 or Y.dim() != 2 or Y.shape[1] != X.shape[1]:
+                raise ValueError("X and Y must be 2-D with the same number of columns")
+            xp[i] = _dev_ptr(X, torch.float64, m.ncols * int(nrhs[i]), "X")
+            yp[i] = _dev_ptr(Y, torch.float64, m.nrows * int(nrhs[i]), "Y")
+        h = C.c_void_p()
+        _check(lib.damn_batch_create(C.byref(h), count, C.cast(hs, C.c_void_p),
+                                     nrhs.ctypes.data_as(C.c_void_p), C.cast(xp, C.c_void_p),
+                                     C.cast(yp, C.c_void_p), float(alpha), float(beta),
+                                     int(workgroups), _stream_ptr(stream)), "batch_create")
+        self._h = h
+        self._keep = (mats, Xs, Ys)
+
+    def run(self, use_graph=True, stream=None):
+        _check(lib.damn_batch_run(self._h, int(bool(use_graph)), _stream_ptr(stream)),
+               "batch_run")
+
+    def info(self):
+        nt, wg, mb = C.c_int64(), C.c_int32(), C.c_double()
+        _check(lib.damn_batch_info(self._h, C.byref(nt), C.byref(wg), C.byref(mb)), "batch_info")
+        return {"ntiles": nt.value, "workgroups": wg.value, "model_bytes": mb.value}
+
+    def destroy(self):
+        if self._h is not None and self._h.value:
+            _check(lib.damn_batch_destroy(self._h), "batch_destroy")
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
 def stream_read(src, sink, stream=None):
     """Streaming-read probe over a contiguous device tensor (bytes % 16 == 0);
     sink: float64 device tensor with at least 65536 entries."""

@@ -64,6 +64,11 @@ _SIGS = {
     "damn_get_config": (C.c_int, [_vp, _vp]),
     "damn_stream_read": (C.c_int, [_vp, C.c_size_t, _vp, _vp]),
     "damn_cg": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "damn_batch_create": (C.c_int, [C.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _f64, _f64, _i32,
+                                    _vp]),
+    "damn_batch_run": (C.c_int, [_vp, _i32, _vp]),
+    "damn_batch_info": (C.c_int, [_vp, _pi64, _pi32, _pf64]),
+    "damn_batch_destroy": (C.c_int, [_vp]),
 }
 
 class _Lib:

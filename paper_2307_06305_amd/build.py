@@ -22,7 +22,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdamn.so")
 
 ARCH = "gfx950"
-HIP_SOURCES = ["api.hip", "spmv_kernels.hip", "cg.hip"]
+HIP_SOURCES = ["api.hip", "spmv_kernels.hip", "cg.hip", "batch.hip"]
 CPP_SOURCES = ["host_format.cpp", "host_rcm.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"]

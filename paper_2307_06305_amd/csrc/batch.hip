@@ -1,0 +1,298 @@
+// Batched DA-CSR SpMM: many matrices of uneven size, each with 1-8
+// right-hand sides, in one persistent launch captured in a HIP graph.
+//
+// At creation the host cuts every matrix into stream tiles (consecutive rows
+// holding at most `cap` entries), lists the tiles of all matrices in order,
+// and splits the list into contiguous ranges of about equal modelled bytes,
+// one range per workgroup.  The kernel walks its range; each tile is copied
+// from HBM into LDS with non-temporal 16-byte direct-to-LDS loads, then every
+// row is reduced by G lanes for all right-hand sides of its matrix at once
+// (X and Y row-major, the nrhs values of a row adjacent).  The static ranges
+// need no atomic work queue and no reset between launches, which keeps the
+// launch replayable from a graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <new>
+#include <vector>
+
+#include "damn.h"
+#include "damn_device.h"
+#include "damn_mat.h"
+
+namespace damn {
+namespace bk {
+
+struct BatchMat {
+  const int32_t* rowptr;
+  const int16_t* off;
+  const double* val;
+  const double* X;
+  double* Y;
+  int32_t nrows;
+  int32_t nrhs;
+  int32_t lanes;
+  int32_t pad;
+};
+
+struct BatchTile {
+  int32_t mat, r0, r1, pad;
+};
+
+template <int NRHS>
+__device__ __forceinline__ void tile_rows(const BatchMat& m, int32_t r0, int32_t r1, int32_t a0,
+                                          const double* __restrict__ val_s,
+                                          const int16_t* __restrict__ idx_s, double alpha,
+                                          double beta, bool read_y) {
+  const int G = m.lanes;
+  const int lane = int(threadIdx.x) % G;
+  for (int32_t r = r0 + int32_t(threadIdx.x) / G; r < r1; r += 256 / G) {
+    const int32_t s = m.rowptr[r] - a0, e = m.rowptr[r + 1] - a0;
+    const double* Xs = m.X + int64_t(r) * NRHS;
+    double acc[NRHS];
+#pragma unroll
+    for (int j = 0; j < NRHS; ++j) acc[j] = 0.0;
+    for (int32_t k = s + lane; k < e; k += G) {
+      const double v = val_s[k];
+      const double* xr = Xs + int64_t(idx_s[k]) * NRHS;
+#pragma unroll
+      for (int j = 0; j < NRHS; ++j) acc[j] += v * xr[j];
+    }
+#pragma unroll
+    for (int j = 0; j < NRHS; ++j) acc[j] = kern::group_sum(acc[j], G);
+    if (lane == 0) {
+      double* yr = m.Y + int64_t(r) * NRHS;
+#pragma unroll
+      for (int j = 0; j < NRHS; ++j) yr[j] = kern::finish(acc[j], alpha, beta, read_y, yr + j);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void batch_spmm(const BatchMat* __restrict__ mats,
+                                                  const BatchTile* __restrict__ tiles,
+                                                  const int32_t* __restrict__ range, int32_t cap,
+                                                  double alpha, double beta, int32_t read_y) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  double* val_s = reinterpret_cast<double*>(lds);
+  int16_t* idx_s = reinterpret_cast<int16_t*>(lds + sizeof(double) * (cap + 16));
+  const uint32_t w = kern::xcd_contiguous(blockIdx.x, gridDim.x);
+  const int32_t t_end = range[w + 1];
+  for (int32_t t = range[w]; t < t_end; ++t) {
+    const BatchTile tile = tiles[t];
+    const BatchMat m = mats[tile.mat];
+    const int32_t p0 = m.rowptr[tile.r0], p1 = m.rowptr[tile.r1];
+    const int32_t a0 = p0 & ~7;
+    __syncthreads();  // the previous tile's readers are done with LDS
+    kern::copy_to_lds(val_s, m.val, a0, p1 - a0);
+    kern::copy_to_lds(idx_s, m.off, a0, p1 - a0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    switch (m.nrhs) {
+      case 1: tile_rows<1>(m, tile.r0, tile.r1, a0, val_s, idx_s, alpha, beta, read_y); break;
+      case 2: tile_rows<2>(m, tile.r0, tile.r1, a0, val_s, idx_s, alpha, beta, read_y); break;
+      case 3: tile_rows<3>(m, tile.r0, tile.r1, a0, val_s, idx_s, alpha, beta, read_y); break;
+      case 4: tile_rows<4>(m, tile.r0, tile.r1, a0, val_s, idx_s, alpha, beta, read_y); break;
+      case 5: tile_rows<5>(m, tile.r0, tile.r1, a0, val_s, idx_s, alpha, beta, read_y); break;
+      case 6: tile_rows<6>(m, tile.r0, tile.r1, a0, val_s, idx_s, alpha, beta, read_y); break;
+      case 7: tile_rows<7>(m, tile.r0, tile.r1, a0, val_s, idx_s, alpha, beta, read_y); break;
+      default: tile_rows<8>(m, tile.r0, tile.r1, a0, val_s, idx_s, alpha, beta, read_y); break;
+    }
+  }
+}
+
+}  // namespace bk
+}  // namespace damn
+
+struct damn_batch_s {
+  int device = 0;
+  int32_t count = 0;
+  int32_t workgroups = 0;
+  int32_t cap = 0;
+  int64_t ntiles = 0;
+  double model_bytes = 0;
+  double alpha = 1.0, beta = 0.0;
+  damn::bk::BatchMat* d_mats = nullptr;
+  damn::bk::BatchTile* d_tiles = nullptr;
+  int32_t* d_range = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace damn {
+namespace {
+
+void free_batch(damn_batch B) {
+  if (!B) return;
+  int cur = 0;
+  hipGetDevice(&cur);
+  hipSetDevice(B->device);
+  if (B->exec) hipGraphExecDestroy(B->exec);
+  if (B->graph) hipGraphDestroy(B->graph);
+  if (B->d_mats) hipFree(B->d_mats);
+  if (B->d_tiles) hipFree(B->d_tiles);
+  if (B->d_range) hipFree(B->d_range);
+  hipSetDevice(cur);
+  delete B;
+}
+
+hipError_t launch_batch(damn_batch B, hipStream_t s) {
+  if (B->ntiles == 0) return hipSuccess;
+  const size_t shmem = size_t(B->cap + 16) * (sizeof(double) + sizeof(int16_t));
+  hipLaunchKernelGGL(bk::batch_spmm, dim3(uint32_t(B->workgroups)), dim3(256), shmem, s,
+                     B->d_mats, B->d_tiles, B->d_range, B->cap, B->alpha, B->beta,
+                     int32_t(B->beta != 0.0));
+  return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace damn
+
+using namespace damn;
+
+extern "C" int damn_batch_create(damn_batch* out, int32_t count, const damn_mat* mats,
+                                 const int32_t* nrhs, const double* const* X,
+                                 double* const* Y, double alpha, double beta,
+                                 int32_t workgroups, void* stream) {
+  if (out == nullptr || count < 0 || (count > 0 && (mats == nullptr || nrhs == nullptr ||
+                                                    X == nullptr || Y == nullptr)))
+    return DAMN_ERR_INVALID_ARG;
+  if (workgroups < 0) return DAMN_ERR_INVALID_ARG;
+  if (workgroups == 0) workgroups = 1024;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // tile cap: at least the longest row, rounded to 8 entries, 2048..4096
+  int32_t longest = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const damn_mat A = mats[i];
+    if (A == nullptr || A->format != DAMN_FORMAT_DA16 || A->dtype != DAMN_F64)
+      return DAMN_ERR_INVALID_ARG;
+    if (nrhs[i] < 1 || nrhs[i] > 8) return DAMN_ERR_UNSUPPORTED;
+    if ((A->nrows > 0 && Y[i] == nullptr) || (A->ncols > 0 && X[i] == nullptr))
+      return DAMN_ERR_INVALID_ARG;
+    const int32_t* rp = A->h_rowptr.data();
+    for (int32_t r = 0; r < A->nrows; ++r) longest = std::max(longest, rp[r + 1] - rp[r]);
+  }
+  int32_t cap = std::max<int32_t>(2048, (longest + 7) / 8 * 8);
+  if (cap > 4096) return DAMN_ERR_UNSUPPORTED;
+
+  std::vector<bk::BatchMat> hm(count);
+  std::vector<bk::BatchTile> ht;
+  std::vector<double> work;  // modelled bytes per tile
+  double total = 0;
+  try {
+    for (int32_t i = 0; i < count; ++i) {
+      const damn_mat A = mats[i];
+      const int32_t k = nrhs[i];
+      const int32_t lanes = A->cfg.variant == DAMN_VAR_STREAM ? std::min(A->cfg.lanes, 16) : 2;
+      hm[i] = {A->d_rowptr, static_cast<const int16_t*>(A->d_idx),
+               static_cast<const double*>(A->d_val), X[i], Y[i], A->nrows, k, lanes, 0};
+      const int32_t* rp = A->h_rowptr.data();
+      int32_t r = 0;
+      while (r < A->nrows) {
+        const int32_t first = r;
+        while (r < A->nrows && r - first < 256 && rp[r + 1] - rp[first] <= cap) ++r;
+        ht.push_back({i, first, r, 0});
+        const double bytes = double(rp[r] - rp[first]) * (2 + 8) +
+                             double(r - first) * (4 + 8.0 * k * (beta != 0.0 ? 2 : 1)) +
+                             double(rp[r] - rp[first]) * 8.0 * k / 4;  // gathers, mostly cached
+        work.push_back(bytes);
+        total += bytes;
+      }
+      total += double(A->ncols) * 8 * k;
+    }
+  } catch (const std::bad_alloc&) {
+    return DAMN_ERR_ALLOC;
+  }
+  const int64_t nt = int64_t(ht.size());
+  if (nt > INT32_MAX) return DAMN_ERR_UNSUPPORTED;
+  // contiguous ranges of about equal work
+  std::vector<int32_t> range(size_t(workgroups) + 1, int32_t(nt));
+  {
+    double tw = 0;
+    for (double v : work) tw += v;
+    const double per = tw / workgroups;
+    double acc = 0;
+    int32_t w = 0;
+    range[0] = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+      acc += work[t];
+      while (w + 1 < workgroups && acc >= per * (w + 1)) range[++w] = int32_t(t + 1);
+    }
+    for (int32_t k = w + 1; k <= workgroups; ++k) range[k] = int32_t(nt);
+  }
+
+  damn_batch B = new (std::nothrow) damn_batch_s();
+  if (!B) return DAMN_ERR_ALLOC;
+  hipGetDevice(&B->device);
+  B->count = count;
+  B->workgroups = workgroups;
+  B->cap = cap;
+  B->ntiles = nt;
+  B->alpha = alpha;
+  B->beta = beta;
+  // modelled bytes of one launch: matrices, row pointers, X read once, Y
+  for (int32_t i = 0; i < count; ++i) {
+    const damn_mat A = mats[i];
+    B->model_bytes += double(A->nnz) * 10 + 4.0 * (A->nrows + 1) +
+                      8.0 * nrhs[i] * (A->ncols + A->nrows * (beta != 0.0 ? 2 : 1));
+  }
+  if (hipMalloc(&B->d_mats, sizeof(bk::BatchMat) * std::max<size_t>(hm.size(), 1)) != hipSuccess ||
+      hipMalloc(&B->d_tiles, sizeof(bk::BatchTile) * std::max<size_t>(ht.size(), 1)) != hipSuccess ||
+      hipMalloc(&B->d_range, sizeof(int32_t) * range.size()) != hipSuccess) {
+    free_batch(B);
+    return DAMN_ERR_ALLOC;
+  }
+  bool ok = (hm.empty() || hipMemcpyAsync(B->d_mats, hm.data(), sizeof(bk::BatchMat) * hm.size(),
+                                          hipMemcpyHostToDevice, s) == hipSuccess) &&
+            (ht.empty() || hipMemcpyAsync(B->d_tiles, ht.data(), sizeof(bk::BatchTile) * ht.size(),
+                                          hipMemcpyHostToDevice, s) == hipSuccess) &&
+            hipMemcpyAsync(B->d_range, range.data(), sizeof(int32_t) * range.size(),
+                           hipMemcpyHostToDevice, s) == hipSuccess &&
+            hipStreamSynchronize(s) == hipSuccess;
+  // capture the launch once into a graph, on a stream of our own
+  hipStream_t cs = nullptr;
+  if (ok) ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+  if (ok) ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    const bool launched = launch_batch(B, cs) == hipSuccess;
+    ok = hipStreamEndCapture(cs, &B->graph) == hipSuccess && launched;
+  }
+  if (ok) ok = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0) == hipSuccess;
+  if (cs) hipStreamDestroy(cs);
+  if (!ok) {
+    free_batch(B);
+    return DAMN_ERR_HIP;
+  }
+  *out = B;
+  return DAMN_OK;
+}
+
+extern "C" int damn_batch_run(damn_batch B, int32_t use_graph, void* stream) {
+  if (B == nullptr) return DAMN_ERR_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (use_graph) {
+    if (B->ntiles == 0) return DAMN_OK;
+    return hipGraphLaunch(B->exec, s) == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
+  }
+  return launch_batch(B, s) == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
+}
+
+extern "C" int damn_batch_info(damn_batch B, int64_t* ntiles, int32_t* workgroups,
+                               double* model_bytes) {
+  if (B == nullptr) return DAMN_ERR_INVALID_ARG;
+  if (ntiles) *ntiles = B->ntiles;
+  if (workgroups) *workgroups = B->workgroups;
+  if (model_bytes) *model_bytes = B->model_bytes;
+  return DAMN_OK;
+}
+
+extern "C" int damn_batch_destroy(damn_batch B) {
+  if (B == nullptr) return DAMN_ERR_INVALID_ARG;
+  int cur = 0;
+  hipGetDevice(&cur);
+  hipSetDevice(B->device);
+  hipDeviceSynchronize();
+  hipSetDevice(cur);
+  free_batch(B);
+  return DAMN_OK;
+}

@@ -16,31 +16,11 @@
 
 #include <cstdint>
 
+#include "damn_device.h"
 #include "damn_kernels.h"
 
 namespace damn {
 namespace kern {
-
-// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
-// XCD b % 8).  Renumber them so each XCD walks one contiguous range of rows:
-// the x window a range touches then stays in that XCD's L2 instead of being
-// fetched by all eight.
-__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t nb) {
-  const uint32_t q = nb >> 3, r = nb & 7u;
-  const uint32_t xcd = b & 7u, pos = b >> 3;
-  return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + pos;
-}
-
-template <typename V>
-__device__ __forceinline__ V group_sum(V v, int width) {
-  for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
-  return v;
-}
-
-template <typename V>
-__device__ __forceinline__ V finish(V acc, V alpha, V beta, bool read_y, const V* y) {
-  return read_y ? alpha * acc + beta * (*y) : alpha * acc;
-}
 
 // ---------------------------------------------------------------------------
 // Vector variant: LANES lanes of a wavefront per row (LANES = 1: one row per
@@ -96,29 +76,6 @@ __global__ __launch_bounds__(256) void spmv_vector(
 // neighbouring rows on neighbouring lanes, so for banded matrices the x
 // gathers of one instruction hit few cache lines.
 // ---------------------------------------------------------------------------
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int kNonTemporal = 2;  // cache-policy bit "nt" of gfx950 loads
-
-// Issue direct-to-LDS copies of elements [a0, a0 + n) of src (a0 a multiple
-// of 8) into dst[0, ...), 16 bytes per lane.  Lane l of wave w copies piece
-// 64*(w + 4*j) + l; every wave writes 1 KiB contiguous blocks of LDS.
-template <typename T>
-__device__ __forceinline__ void copy_to_lds(T* __restrict__ dst, const T* __restrict__ src,
-                                            int32_t a0, int32_t n) {
-#if defined(__HIP_DEVICE_COMPILE__)  // the builtin exists only in the device pass
-  constexpr int32_t kPer = 16 / int32_t(sizeof(T));  // elements per piece
-  const int32_t pieces = (n + kPer - 1) / kPer;
-  const int32_t wave = int32_t(threadIdx.x >> 6), lane = int32_t(threadIdx.x & 63);
-  for (int32_t base = wave * 64; base < pieces; base += 256) {
-    const int32_t q = base + lane;
-    if (q < pieces)
-      __builtin_amdgcn_global_load_lds(src + a0 + kPer * q, dst + kPer * base, 16, 0,
-                                       kNonTemporal);
-  }
-#endif
-}
-
 // Workgroup sum of one double per thread, in a fixed order (wave sums, then
 // the four wave results left to right); the result is valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* scratch4) {

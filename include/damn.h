@@ -288,6 +288,76 @@ int damn_batch_info(damn_batch B, int64_t* ntiles, int32_t* workgroups, double* 
 int damn_batch_destroy(damn_batch B);
 
 /* ------------------------------------------------------------------------
+ * Choosing a launch configuration.  The paper picks, per matrix, the
+ * fastest of its implementations and thread counts (Sec. 4.1); here an
+ * exhaustive autotuner measures every configuration, and a small network
+ * trained on the autotuner's measurements predicts the choice from
+ * sparsity features.
+ * --------------------------------------------------------------------- */
+
+#define DAMN_NFEAT 16
+#define DAMN_NCLASS 49
+#define DAMN_MLP_NPARAMS 8465
+
+/* Sparsity features of an int32 CSR matrix (host, float64 arithmetic,
+ * float32 results): 0 log2(nrows+1), 1 log2(nnz+1), 2 mean row length,
+ * 3 std of row lengths, 4 log2(max row length+1), 5 fraction of empty rows,
+ * 6 log2(w+1), 7 w/max(ncols,1), 8 w >= 32768, 9 nrhs,
+ * 10 log2(mean |c-r| + 1), 11 fraction of entries with |c-r| <= 64,
+ * 12 std/mean of row lengths, 13 fraction of rows with >= 64 entries,
+ * 14 log2(ncols+1), 15 fraction of adjacent entry pairs within a row whose
+ * columns differ by 1.  w is the bandwidth of Eq. 2.
+ * Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_BAD_CSR. */
+int damn_features(int32_t nrows, int32_t ncols, const int32_t* rowptr,
+                  const int32_t* colids, int32_t nrhs, float* feat);
+
+/* Configuration of class cls (0 <= cls < DAMN_NCLASS): classes 0..20 are
+ * the vector variant (lanes 1..64 x unroll 1,2,4), 21..41 the stream variant
+ * (lanes 1..64 x tile 1024, 2048, 4096), both for nrhs = 1; 42..48 are SpMM
+ * lane counts 1..64 for nrhs > 1 (*spmm = 1). */
+int damn_class_config(int32_t cls, damn_config* cfg, int32_t* spmm);
+
+/* Time every class that applies to nrhs (reps launches each after one
+ * warm-up, HIP events on `stream`), write seconds per launch to
+ * times[DAMN_NCLASS] (+inf for classes that do not apply) and set the
+ * fastest configuration on A.  X, Y: device operands as for damn_spmv
+ * (nrhs = 1, the handle's dtype) or damn_spmm (nrhs > 1, float64).  Y is
+ * overwritten.  Synchronises the stream.
+ * Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_UNSUPPORTED, DAMN_ERR_HIP. */
+int damn_autotune(damn_mat A, int32_t nrhs, const void* X, void* Y, int32_t reps,
+                  float* times, void* stream);
+
+typedef struct damn_mlp_s* damn_mlp;
+
+/* Network 16 -> 64 -> 64 -> 49 (ReLU), float32 on the device.  params
+ * (host, DAMN_MLP_NPARAMS floats: W1[64][16], b1, W2[64][64], b2, W3[49][64],
+ * b3, then the feature standardisation mu[16], sigma[16]) or NULL for a
+ * seeded He-uniform initialisation. */
+int damn_mlp_create(damn_mlp* out, const float* params, uint64_t seed);
+int damn_mlp_get_params(damn_mlp M, float* params);
+int damn_mlp_destroy(damn_mlp M);
+
+/* Loss and parameter gradients on one minibatch (for checking the backward
+ * kernels): feats[B][16], targets[B][49] (a distribution over the classes
+ * that apply; feats[b][9] = nrhs decides which apply), host arrays; the
+ * gradients of mu and sigma are returned as 0. */
+int damn_mlp_grad(damn_mlp M, int32_t B, const float* feats, const float* targets, float* loss,
+                  float* grads, void* stream);
+
+/* Train on N samples: feats[N][16] and autotuner times[N][49] (+inf where a
+ * class does not apply), host arrays.  Sets mu/sigma from the features, then
+ * runs `epochs` passes of Adam over shuffled minibatches of `batch` samples
+ * with soft targets q_c ~ exp(-(t_c/t_min - 1)/tau).  epoch_loss[epochs]
+ * (may be NULL) receives the mean loss of each pass. */
+int damn_mlp_train(damn_mlp M, int32_t N, const float* feats, const float* times,
+                   int32_t epochs, int32_t batch, float lr, float tau, uint64_t seed,
+                   float* epoch_loss, void* stream);
+
+/* Predicted class for N feature rows (host in, host out), by the inference
+ * kernel: the most probable class that applies to the row's nrhs. */
+int damn_select(damn_mlp M, int32_t N, const float* feats, int32_t* cls, void* stream);
+
+/* ------------------------------------------------------------------------
  * Measurement helpers.
  * --------------------------------------------------------------------- */
 

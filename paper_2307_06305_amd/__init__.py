@@ -337,6 +337,112 @@ class Batch:
             pass
 
 
+NFEAT, NCLASS, MLP_NPARAMS = 16, 49, 8465
+
+
+def features(nrows, ncols, rowptr, colids, nrhs):
+    """The 16 sparsity features of an int32 CSR matrix (host), float32."""
+    c = _i32(colids)
+    rp = _csr_arrays(nrows, rowptr, c)
+    f = np.empty(NFEAT, dtype=np.float32)
+    _check(lib.damn_features(nrows, ncols, _ptr(rp, C.c_int32), _ptr(c, C.c_int32), int(nrhs),
+                             f.ctypes.data_as(C.c_void_p)), "features")
+    return f
+
+
+def class_config(cls):
+    """(variant, lanes, unroll, tile, spmm) of selector class cls."""
+    cfg = _Config()
+    mm = C.c_int32()
+    _check(lib.damn_class_config(int(cls), C.addressof(cfg), C.byref(mm)), "class_config")
+    return cfg.variant, cfg.lanes, cfg.unroll, cfg.tile, bool(mm.value)
+
+
+def autotune(mat, nrhs, X, Y, reps=3, stream=None):
+    """Time every applicable class on the device and set the fastest on mat.
+    Returns float32 seconds per launch for the NCLASS classes (+inf where a
+    class does not apply)."""
+    import torch
+
+    if nrhs == 1:
+        dt = mat.torch_dtype
+        xp = _dev_ptr(X, dt, mat.ncols, "x")
+        yp = _dev_ptr(Y, dt, mat.nrows, "y")
+    else:
+        xp = _dev_ptr(X, torch.float64, mat.ncols * nrhs, "X")
+        yp = _dev_ptr(Y, torch.float64, mat.nrows * nrhs, "Y")
+    t = np.empty(NCLASS, dtype=np.float32)
+    _check(lib.damn_autotune(mat.handle, int(nrhs), xp, yp, int(reps), t.ctypes.data_as(C.c_void_p),
+                             _stream_ptr(stream)), "autotune")
+    return t
+
+
+class Mlp:
+    """The selector network on the device."""
+
+    def __init__(self, params=None, seed=0):
+        h = C.c_void_p()
+        p = None
+        if params is not None:
+            p = np.ascontiguousarray(params, dtype=np.float32)
+            if p.shape != (MLP_NPARAMS,):
+                raise ValueError(f"params must have {MLP_NPARAMS} floats")
+        _check(lib.damn_mlp_create(C.byref(h), None if p is None else p.ctypes.data_as(C.c_void_p),
+                                   C.c_uint64(seed)), "mlp_create")
+        self._h = h
+
+    def params(self):
+        out = np.empty(MLP_NPARAMS, dtype=np.float32)
+        _check(lib.damn_mlp_get_params(self._h, out.ctypes.data_as(C.c_void_p)), "mlp_get_params")
+        return out
+
+    def grad(self, feats, targets, stream=None):
+        F = np.ascontiguousarray(feats, dtype=np.float32)
+        Q = np.ascontiguousarray(targets, dtype=np.float32)
+        B = F.shape[0]
+        if F.shape != (B, NFEAT) or Q.shape != (B, NCLASS):
+            raise ValueError("feats (B, 16) and targets (B, 49)")
+        loss = C.c_float()
+        g = np.empty(MLP_NPARAMS, dtype=np.float32)
+        _check(lib.damn_mlp_grad(self._h, B, F.ctypes.data_as(C.c_void_p),
+                                 Q.ctypes.data_as(C.c_void_p), C.byref(loss),
+                                 g.ctypes.data_as(C.c_void_p), _stream_ptr(stream)), "mlp_grad")
+        return loss.value, g
+
+    def train(self, feats, times, epochs=200, batch=256, lr=3e-3, tau=0.05, seed=0,
+              stream=None):
+        F = np.ascontiguousarray(feats, dtype=np.float32)
+        T = np.ascontiguousarray(times, dtype=np.float32)
+        N = F.shape[0]
+        if F.shape != (N, NFEAT) or T.shape != (N, NCLASS):
+            raise ValueError("feats (N, 16) and times (N, 49)")
+        losses = np.empty(epochs, dtype=np.float32)
+        _check(lib.damn_mlp_train(self._h, N, F.ctypes.data_as(C.c_void_p),
+                                  T.ctypes.data_as(C.c_void_p), int(epochs), int(batch),
+                                  C.c_float(lr), C.c_float(tau), C.c_uint64(seed),
+                                  losses.ctypes.data_as(C.c_void_p), _stream_ptr(stream)),
+               "mlp_train")
+        return losses
+
+    def select(self, feats, stream=None):
+        F = np.ascontiguousarray(np.atleast_2d(feats), dtype=np.float32)
+        out = np.empty(F.shape[0], dtype=np.int32)
+        _check(lib.damn_select(self._h, F.shape[0], F.ctypes.data_as(C.c_void_p),
+                               out.ctypes.data_as(C.c_void_p), _stream_ptr(stream)), "select")
+        return out
+
+    def destroy(self):
+        if self._h is not None and self._h.value:
+            _check(lib.damn_mlp_destroy(self._h), "mlp_destroy")
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
 def stream_read(src, sink, stream=None):
     """Streaming-read probe over a contiguous device tensor (bytes % 16 == 0);
     sink: float64 device tensor with at least 65536 entries."""

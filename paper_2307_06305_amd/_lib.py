@@ -69,6 +69,16 @@ _SIGS = {
     "damn_batch_run": (C.c_int, [_vp, _i32, _vp]),
     "damn_batch_info": (C.c_int, [_vp, _pi64, _pi32, _pf64]),
     "damn_batch_destroy": (C.c_int, [_vp]),
+    "damn_features": (C.c_int, [_i32, _i32, _pi32, _pi32, _i32, _vp]),
+    "damn_class_config": (C.c_int, [_i32, _vp, _pi32]),
+    "damn_autotune": (C.c_int, [_vp, _i32, _vp, _vp, _i32, _vp, _vp]),
+    "damn_mlp_create": (C.c_int, [C.POINTER(_vp), _vp, C.c_uint64]),
+    "damn_mlp_get_params": (C.c_int, [_vp, _vp]),
+    "damn_mlp_destroy": (C.c_int, [_vp]),
+    "damn_mlp_grad": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "damn_mlp_train": (C.c_int, [_vp, _i32, _vp, _vp, _i32, _i32, C.c_float, C.c_float,
+                                 C.c_uint64, _vp, _vp]),
+    "damn_select": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
 }
 
 class _Lib:

@@ -1,0 +1,146 @@
+"""The kernel selector on the GPU: network gradients and inference against
+the float64 oracle, training, the autotuner, and what the shipped network
+gains over the library's default configuration on matrices it never saw."""
+
+import os
+
+import numpy as np
+import pytest
+
+import paper_2307_06305_amd as D
+from gpu_util import dev, torch_or_skip
+from oracle import mlp as OM
+from paper_2307_06305_amd import selector as S
+from paper_2307_06305_amd.tuning import candidates
+from workloads.matrices import batch_matrix, batch_member
+
+pytestmark = pytest.mark.gpu
+
+K = D.NCLASS
+
+
+def _mask(F):
+    spmm = F[:, 9] > 1.5
+    cls = np.arange(K)
+    return np.where(spmm[:, None], cls[None, :] >= 42, cls[None, :] < 42)
+
+
+def _params(seed):
+    rng = np.random.default_rng(seed)
+    net = D.Mlp(seed=seed)
+    p = net.params()
+    net.destroy()
+    p[OM.nparams(K) - 32:OM.nparams(K) - 16] = rng.standard_normal(16)           # mu
+    p[OM.nparams(K) - 16:] = rng.uniform(0.5, 2.0, 16)                           # sigma
+    p[:OM.nparams(K) - 32] += rng.standard_normal(OM.nparams(K) - 32) * 0.05
+    return p.astype(np.float32)
+
+
+def _batch(B, seed):
+    rng = np.random.default_rng(seed)
+    F = rng.standard_normal((B, 16)).astype(np.float32)
+    F[:, 9] = rng.choice([1.0, 4.0], B)
+    times = rng.uniform(1.0, 2.0, (B, K))
+    times[~_mask(F)] = np.inf
+    Q, _ = OM.soft_targets(times, 0.1)
+    return F, Q.astype(np.float32)
+
+
+def test_gradients_match_oracle():
+    torch_or_skip()
+    p = _params(3)
+    F, Q = _batch(40, 4)
+    net = D.Mlp(p)
+    loss, g = net.grad(F, Q)
+    net.destroy()
+    P = OM.unpack(p.astype(np.float64), K)
+    lref, gref = OM.backward(P, F.astype(np.float64), _mask(F), Q.astype(np.float64))
+    assert abs(loss - lref) <= 1e-4 * abs(lref)
+    off = 0
+    for name, shp in OM.shapes(K):
+        size = int(np.prod(shp))
+        got = g[off:off + size].reshape(shp)
+        ref = gref[name]
+        scale = np.abs(ref).max()
+        assert np.abs(got - ref).max() <= 1e-4 * scale + 1e-7, name
+        off += size
+    assert np.all(g[off:] == 0)
+
+
+def test_select_matches_oracle_argmax():
+    torch_or_skip()
+    p = _params(5)
+    F, _ = _batch(300, 6)
+    net = D.Mlp(p)
+    got = net.select(F)
+    net.destroy()
+    P = OM.unpack(p.astype(np.float64), K)
+    mask = _mask(F)
+    ref = OM.select(P, F.astype(np.float64), mask)
+    Z = np.where(mask, OM.forward(P, F.astype(np.float64), mask)["Z"], -np.inf)
+    top2 = np.sort(Z, axis=1)[:, -2:]
+    clear = top2[:, 1] - top2[:, 0] > 1e-3
+    assert clear.sum() > 250
+    assert np.array_equal(got[clear], ref[clear])
+    assert np.all(mask[np.arange(len(F)), got])
+
+
+def test_training_reduces_loss():
+    torch_or_skip()
+    rng = np.random.default_rng(0)
+    N = 2048
+    F = rng.standard_normal((N, 16)).astype(np.float32)
+    F[:, 9] = 1.0
+    best = (F[:, 0] > 0).astype(int) * 3 + (F[:, 1] > 0).astype(int) * 21
+    T = np.full((N, K), 2.0, dtype=np.float32)
+    T[:, 42:] = np.inf
+    T[np.arange(N), best] = 1.0
+    net = D.Mlp(seed=2)
+    losses = net.train(F, T, epochs=40, batch=128, lr=3e-3, tau=0.05, seed=3)
+    acc = np.mean(net.select(F) == best)
+    net.destroy()
+    assert losses[-1] < 0.2 * losses[0]
+    assert acc > 0.95
+
+
+def test_autotune_sets_fastest_class():
+    torch = torch_or_skip()
+    d = batch_member(9, 1, n_lo=2e4, n_hi=3e4)
+    A = batch_matrix(d)
+    e = D.encode(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, allow_rcm=False)
+    M = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], e["vals"])
+    x = dev(np.ones(A.ncols))
+    y = torch.zeros(A.nrows, dtype=torch.float64, device="cuda")
+    t = D.autotune(M, 1, x, y, reps=2)
+    assert np.all(np.isfinite(t[:42])) and np.all(np.isinf(t[42:]))
+    assert S.config_class(M.get_config(), 1) == int(np.argmin(t))
+    X = dev(np.ones((A.ncols, 3)))
+    Y = torch.zeros(A.nrows, 3, dtype=torch.float64, device="cuda")
+    t3 = D.autotune(M, 3, X, Y, reps=2)
+    assert np.all(np.isinf(t3[:42])) and np.all(np.isfinite(t3[42:]))
+    assert S.config_class(M.get_config(), 3) == 42 + int(np.argmin(t3[42:]))
+    M.destroy()
+
+
+def test_class_table_matches_tuning_candidates():
+    for k, c in enumerate(candidates()):
+        v, l, u, tile, mm = D.class_config(k)
+        assert (v, l) == c[:2] and not mm
+        if v == 0:
+            assert u == c[2]
+        else:
+            assert tile == c[3]
+
+
+def test_shipped_selector_beats_the_default_on_unseen_matrices():
+    """Matrices from seeds the network was not trained on: the shipped
+    network's choice against the library default (no selector) and against
+    the exhaustive autotuner."""
+    torch_or_skip()
+    assert os.path.exists(S.WEIGHTS), "trained selector weights are missing"
+    data = S.collect(24, seed=6006, reps=3)
+    res = S.evaluate(S.load_weights(), data["F"], data["T"], data["default"])
+    print(res)
+    assert res["mean_regret"] < res["default_mean_slowdown"]
+    assert res["time_ratio_default_over_selected"] > 1.0
+    assert res["mean_regret"] <= 0.10

@@ -197,7 +197,7 @@ def bench_batch(D, args):
 
     dev = torch.device("cuda:0")
     count = args.batch_count
-    mats, Xs, Ys, lanes_best = [], [], [], []
+    mats, Xs, Ys, shapes = [], [], [], []
     total_nnz = total_rows = 0
     t0 = time.time()
     for i in range(count):
@@ -210,25 +210,39 @@ def bench_batch(D, args):
         Xs.append((torch.rand(A.ncols, k, generator=g, dtype=torch.float64) * 2 - 1).to(dev))
         Ys.append(torch.zeros(A.nrows, k, dtype=torch.float64, device=dev))
         mats.append(M)
+        shapes.append((D.features(A.nrows, A.ncols, A.rowptr, A.colids, 1),
+                       D.features(A.nrows, A.ncols, A.rowptr, A.colids, k)))
         total_nnz += A.nnz
         total_rows += A.nrows
     log(f"batch: {count} matrices, {total_rows} rows, {total_nnz} entries "
         f"({time.time() - t0:.1f}s to build)")
-    # separate launches: tune each matrix's SpMM lanes
-    for M, X, Y in zip(mats, Xs, Ys):
-        best = None
-        for l in (1, 2, 4, 8, 16, 32):
-            M.set_config(D.VAR_VECTOR, l, 1, 2048)
-            t = time_launches(lambda: M.spmm(X, Y), 3)
-            if best is None or t < best[0]:
-                best = (t, l)
-        lanes_best.append(best[1])
-    for M, l in zip(mats, lanes_best):
-        M.set_config(D.VAR_VECTOR, l, 1, 2048)
+    # separate launches: the native autotuner picks each matrix's SpMV and
+    # SpMM configuration (the SpMM one stays set); its timings also score the
+    # shipped selector network against the exhaustive search
+    from paper_2307_06305_amd import selector as S
+
+    feats, times, default = [], [], []
+    for M, X, Y, A_shape in zip(mats, Xs, Ys, shapes):
+        default_cfg = M.get_config()
+        k = X.shape[1]
+        x1 = X[:, 0].contiguous()
+        y1 = torch.zeros(M.nrows, dtype=torch.float64, device=dev)
+        times.append(D.autotune(M, 1, x1, y1, reps=3))
+        feats.append(A_shape[0])
+        default.append(S.config_class(default_cfg, 1))
+        if k > 1:
+            times.append(D.autotune(M, k, X, Y, reps=3))
+            feats.append(A_shape[1])
+            default.append(S.config_class(default_cfg, k))
+    sel = S.evaluate(S.load_weights(), np.array(feats), np.array(times), np.array(default))
+    log(f"selector on the batch matrices: {sel}")
 
     def separate():
         for M, X, Y in zip(mats, Xs, Ys):
-            M.spmm(X, Y)
+            if X.shape[1] == 1:
+                M.apply(X.view(-1), Y.view(-1))
+            else:
+                M.spmm(X, Y)
 
     t_sep = epochs(separate, 3, 3)
     # one persistent launch; each matrix reduces rows with the default lane
@@ -249,11 +263,33 @@ def bench_batch(D, args):
            "graph_us": round(t_graph * 1e6, 1), "graph_gbs": round(T / t_graph / 1e9, 1),
            "direct_us": round(t_direct * 1e6, 1),
            "separate_us": round(t_sep * 1e6, 1), "separate_gbs": round(T / t_sep / 1e9, 1),
-           "speedup_vs_separate": round(t_sep / t_graph, 3)}
+           "speedup_vs_separate": round(t_sep / t_graph, 3),
+           "selector": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sel.items()}}
     log(f"batch: {res}")
     B.destroy()
     for M in mats:
         M.destroy()
+    return res
+
+
+def bench_selector_training(D, args):
+    """Train a fresh selector network on the shipped autotuner dataset with
+    the library's GPU training kernels; score it on the held-out matrices."""
+    import numpy as np
+
+    from paper_2307_06305_amd import selector as S
+
+    d = np.load(S.DATASET, allow_pickle=False)
+    data = {k: d[k] for k in d.files}
+    tr, ho = S.split(data)
+    t0 = time.time()
+    params, losses = S.train(data["F"][tr], data["T"][tr], epochs=300, seed=11)
+    dt = time.time() - t0
+    ev = S.evaluate(params, data["F"][ho], data["T"][ho], data["default"][ho])
+    res = {"train_samples": int(tr.sum()), "heldout_samples": int(ho.sum()), "train_s": round(dt, 2),
+           "loss_first": round(float(losses[0]), 4), "loss_last": round(float(losses[-1]), 4),
+           **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in ev.items()}}
+    log(f"selector training: {res}")
     return res
 
 
@@ -392,6 +428,7 @@ def main():
         res["cg"] = bench_cg(D, args)
     if not args.skip_batch:
         res["batch"] = bench_batch(D, args)
+        res["selector_training"] = bench_selector_training(D, args)
 
     if not args.no_cpu:
         t_cpu, reps = cpu_baseline(A, e, x)

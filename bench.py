@@ -306,6 +306,9 @@ def main():
     ap.add_argument("--skip-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-workgroups", type=int, default=0)
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for counter collection: copy probe, then DA and CSR SpMV "
+                         "with the default stream configuration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
@@ -339,6 +342,23 @@ def main():
     xd = torch.from_numpy(x).to(dev)
     yd = torch.zeros(A.nrows, dtype=torch.float64, device=dev)
     yc = torch.zeros_like(yd)
+
+    if args.profile:
+        # counter runs: a copy of known size, then the two products
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            D.stream_copy(src, dst)
+        del src, dst
+        M.set_config(D.VAR_STREAM, 2, 1, 2048)
+        Cm.set_config(D.VAR_STREAM, 2, 1, 2048)
+        for _ in range(10):
+            M.spmv(xd, yd)
+        for _ in range(10):
+            Cm.csr_spmv(xd, yc)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": "done", "copy_bytes": 1 << 30}), flush=True)
+        return
 
     # streaming ceiling: a plain 16-byte-load read of 2 GiB
     buf = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
@@ -388,6 +408,14 @@ def main():
 
     W = 2 * A.nnz + 2 * A.nrows
     da_gbs = T_da / t_da_events / 1e9
+    # HBM bytes per launch from the recorded counter runs, while the kernel
+    # sources are unchanged and the timed launch shape is the profiled one
+    from paper_2307_06305_amd.profiling import read_traffic
+
+    traffic = None
+    if config_name(best_da) == "stream_g2_t2048":
+        tb = read_traffic(os.path.join(ROOT, "profiles", "spmv_27pt128_traffic.md"))
+        traffic = None if tb is None else int(round(tb))
     res = {
         "metric": "DA-CSR vs CSR SpMV effective GB/s, % HBM peak, speedup; CG time to 1e-10",
         "value": round(T_da / (ms_per_step * 1e-3) / 1e9, 1),
@@ -405,7 +433,8 @@ def main():
                    "bandwidth": e["w"], "index": "int16 DA offsets", "values": "f64",
                    "launch": config_name(best_da)},
         "roofline": {"bound": "hbm", "achieved": round(da_gbs, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(da_gbs / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(da_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
         "da": {"us": round(t_da * 1e6, 2), "model_bytes": T_da,
                "gbs": round(T_da / t_da / 1e9, 1),
                "pct_hbm_peak": round(100 * T_da / t_da / 1e9 / HBM_PEAK_GBS, 2),

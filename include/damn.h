@@ -367,6 +367,11 @@ int damn_select(damn_mlp M, int32_t N, const float* feats, int32_t* cls, void* s
  * and to calibrate traffic counters.  Errors: DAMN_ERR_INVALID_ARG. */
 int damn_stream_read(const void* src, size_t bytes, double* sink, void* stream);
 
+/* Copy probe: dst = src for `bytes` (multiple of 16) with 16-byte accesses;
+ * known bytes read and written, to calibrate memory-traffic counters.
+ * Errors: DAMN_ERR_INVALID_ARG. */
+int damn_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

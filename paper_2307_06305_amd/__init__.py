@@ -458,5 +458,17 @@ def stream_read(src, sink, stream=None):
                                 C.c_void_p(sink.data_ptr()), _stream_ptr(stream)), "stream_read")
 
 
+def stream_copy(src, dst, stream=None):
+    """Copy probe between two contiguous device tensors of equal byte size
+    (a multiple of 16)."""
+    nbytes = src.numel() * src.element_size()
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous device tensors")
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst sizes differ")
+    _check(lib.damn_stream_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                                C.c_size_t(nbytes), _stream_ptr(stream)), "stream_copy")
+
+
 def library_path() -> str:
     return os.path.abspath(LIB_PATH)

@@ -340,4 +340,12 @@ int damn_stream_read(const void* src, size_t bytes, double* sink, void* stream) 
   return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
 }
 
+int damn_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  if (((src == nullptr || dst == nullptr) && bytes > 0) || bytes % 16 != 0)
+    return DAMN_ERR_INVALID_ARG;
+  const hipError_t e =
+      launch_stream_copy(src, dst, int64_t(bytes), static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
+}
+
 }  // extern "C"

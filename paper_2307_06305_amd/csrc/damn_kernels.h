@@ -40,5 +40,6 @@ hipError_t launch_spmv_dot(const SpmvArgs& a, int lanes, const void* w, double* 
 // float64 only; 1 <= nrhs <= 8
 hipError_t launch_spmm(const SpmvArgs& a, int lanes, int nrhs);
 hipError_t launch_stream_read(const void* src, int64_t bytes, double* sink, hipStream_t s);
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
 
 }  // namespace damn

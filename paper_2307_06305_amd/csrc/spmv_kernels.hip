@@ -230,6 +230,17 @@ __global__ __launch_bounds__(256) void stream_read(const u32x4* __restrict__ src
   }
 }
 
+// Copy probe: dst = src in 16-byte pieces, one contiguous slice per
+// workgroup (known bytes read and written, to calibrate traffic counters).
+__global__ __launch_bounds__(256) void stream_copy(const u32x4* __restrict__ src,
+                                                   u32x4* __restrict__ dst, int64_t n16) {
+  const uint32_t b = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int64_t per = (n16 + gridDim.x - 1) / gridDim.x;
+  const int64_t s = int64_t(b) * per;
+  const int64_t e = s + per < n16 ? s + per : n16;
+  for (int64_t i = s + threadIdx.x; i < e; i += 256) dst[i] = __builtin_nontemporal_load(src + i);
+}
+
 }  // namespace kern
 
 // ---------------------------------------------------------------------------
@@ -419,6 +430,17 @@ hipError_t launch_spmm(const SpmvArgs& a, int lanes, int nrhs) {
   }
   return a.da ? launch_spmm<int16_t, true>(a, lanes, nrhs)
               : launch_spmm<int32_t, false>(a, lanes, nrhs);
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t s) {
+  const int64_t n16 = bytes / 16;
+  if (n16 == 0) return hipSuccess;
+  int64_t blocks = n16 / 4096;
+  if (blocks < 256) blocks = 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(kern::stream_copy, dim3(uint32_t(blocks)), dim3(256), 0, s,
+                     static_cast<const kern::u32x4*>(src), static_cast<kern::u32x4*>(dst), n16);
+  return hipGetLastError();
 }
 
 hipError_t launch_stream_read(const void* src, int64_t bytes, double* sink, hipStream_t s) {

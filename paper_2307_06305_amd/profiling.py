@@ -1,0 +1,141 @@
+"""Memory-traffic measurement from rocprofv3 counters.
+
+Two counter runs of `bench.py --profile` (one with FETCH_SIZE, one with
+WRITE_SIZE, both in KiB per dispatch) give the HBM bytes of the SpMV kernels.
+Each counter is scaled by what it reads for the copy probe of known size
+(`damn_stream_copy`), launched in the same run:
+
+    bytes = counter_KiB * 1024 / (copy_counter_KiB * 1024 / copy_bytes)
+
+    python -m paper_2307_06305_amd.profiling summarize \\
+        --fetch <fetch run>/run_counter_collection.csv \\
+        --write <write run>/run_counter_collection.csv \\
+        --copy-bytes 1073741824 --out profiles/spmv_27pt128_traffic.md
+
+The summary records a hash of the kernel sources; bench.py reports the
+traffic only while the sources still hash the same.
+"""
+
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import re
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("csrc/spmv_kernels.hip", "csrc/damn_device.h")
+DA_KERNEL = "spmv_stream<short, double, true, 2, false>"
+CSR_KERNEL = "spmv_stream<int, double, false, 2, false>"
+COPY_KERNEL = "stream_copy"
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(PKG, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _per_kernel(path, counter):
+    """Mean counter value per dispatch, by kernel name."""
+    sums, counts = {}, {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row["Counter_Name"] != counter:
+                continue
+            name = row["Kernel_Name"]
+            sums[name] = sums.get(name, 0.0) + float(row["Counter_Value"])
+            counts[name] = counts.get(name, 0) + 1
+    return {k: (sums[k] / counts[k], counts[k]) for k in sums}
+
+
+def _find(table, needle):
+    for name, v in table.items():
+        if needle in name:
+            return v
+    raise KeyError(f"no kernel matching {needle!r}")
+
+
+def summarize(fetch_csv, write_csv, copy_bytes):
+    fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
+    write = _per_kernel(write_csv, "WRITE_SIZE")
+    cf = _find(fetch, COPY_KERNEL)[0] * 1024 / copy_bytes
+    cw = _find(write, COPY_KERNEL)[0] * 1024 / copy_bytes
+    out = {"copy_bytes": copy_bytes, "fetch_scale": cf, "write_scale": cw,
+           "source_sha256": kernel_source_hash(), "kernels": {}}
+    for label, needle in (("da", DA_KERNEL), ("csr", CSR_KERNEL)):
+        fk, nf = _find(fetch, needle)
+        wk, nw = _find(write, needle)
+        out["kernels"][label] = {
+            "kernel": needle, "dispatches": [nf, nw], "fetch_kib": fk, "write_kib": wk,
+            "hbm_read_bytes": fk * 1024 / cf, "hbm_write_bytes": wk * 1024 / cw,
+            "hbm_bytes": fk * 1024 / cf + wk * 1024 / cw}
+    return out
+
+
+def write_summary(summary, path, command):
+    da, csr = summary["kernels"]["da"], summary["kernels"]["csr"]
+    lines = [
+        "# HBM traffic: DA-CSR and CSR SpMV, 3D 27-point stencil 128^3",
+        "",
+        "Counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch), one rocprofv3 run each:",
+        "",
+        "```",
+        command,
+        "```",
+        "",
+        f"Copy probe ({summary['copy_bytes']} bytes read and written): FETCH_SIZE reads "
+        f"{summary['fetch_scale']:.4f} and WRITE_SIZE {summary['write_scale']:.4f} of the "
+        "known bytes; the kernels' counters are divided by these factors.",
+        "",
+        "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM read B | HBM write B | total B |",
+        "|---|---:|---:|---:|---:|---:|",
+    ]
+    for k in (da, csr):
+        lines.append(f"| `{k['kernel']}` | {k['fetch_kib']:.0f} | {k['write_kib']:.0f} | "
+                     f"{k['hbm_read_bytes']:.4g} | {k['hbm_write_bytes']:.4g} | "
+                     f"{k['hbm_bytes']:.4g} |")
+    lines += ["", "Traffic model (Eq. 3 plus x once and y written): DA 599,372,724 B, "
+              "CSR 710,858,660 B.", "", "```json", json.dumps(summary, indent=1), "```", ""]
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
+
+
+def read_traffic(path, label="da"):
+    """HBM bytes per launch recorded in a summary, or None if the summary is
+    missing or the kernel sources changed since it was taken."""
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    s = json.loads(m.group(1))
+    if s.get("source_sha256") != kernel_source_hash():
+        return None
+    return s["kernels"][label]["hbm_bytes"]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="python -m paper_2307_06305_amd.profiling")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("summarize")
+    s.add_argument("--fetch", required=True)
+    s.add_argument("--write", required=True)
+    s.add_argument("--copy-bytes", type=int, required=True)
+    s.add_argument("--out", required=True)
+    s.add_argument("--command", default="")
+    a = ap.parse_args(argv)
+    summary = summarize(a.fetch, a.write, a.copy_bytes)
+    write_summary(summary, a.out, a.command)
+    print(json.dumps(summary["kernels"]), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

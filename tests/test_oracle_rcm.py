@@ -79,15 +79,13 @@ def test_george_liu_search_changes_start_by_hand():
 
 
 def test_search_moves_to_farther_vertex_by_hand():
-    # path 0-1-2-3-4 where vertex 2 also has leaf 5... but the unique
-    # smallest-(deg,index) seed is the isolated-free leaf 0 which is already
-    # peripheral; to force a move, make the seed a middle vertex of degree 1:
-    # graph: 0-1, 1-2, 2-3, 1-4, 4-5 ... deg: 0:1, 1:3, 2:2, 3:1, 4:2, 5:1.
-    # Seed 0.  Levels from 0: {0},{1},{2,4},{3,5}: 4 levels; last level min is
-    # 3; levels from 3: {3},{2},{1},{0,4},{5}: 5 levels -> move to 3.  From 3 the
-    # last level {5}: levels from 5: {5},{4},{1},{0,2},{3}: 5, not more -> 3.
-    # CM from 3: 3, 2, 1, then 1's list by (deg,index): 0 (deg 1), 4 (deg 2);
-    # then 4 adds 5.  Order 3,2,1,0,4,5; reversed 5,4,0,1,2,3.
+    # graph 0-1, 1-2, 2-3, 1-4, 4-5; deg: 0:1, 1:3, 2:2, 3:1, 4:2, 5:1.
+    # Seed 0.  Levels from 0: {0},{1},{2,4},{3,5}: 4 levels; the last level's
+    # smallest (deg,index) is 3; levels from 3: {3},{2},{1},{0,4},{5}: 5
+    # levels -> move to 3.  From 3 the last level is {5}: levels from 5:
+    # {5},{4},{1},{0,2},{3}: 5, not more -> start 3.  CM from 3: 3, 2, 1,
+    # then 1's list by (deg,index): 0 (deg 1), 4 (deg 2); then 4 adds 5.
+    # Order 3,2,1,0,4,5; reversed 5,4,0,1,2,3.
     edges = [(0, 1), (1, 2), (2, 3), (1, 4), (4, 5)]
     rp, c = _csr_from_edges(6, edges)
     assert R.rcm(6, rp, c).tolist() == [5, 4, 0, 1, 2, 3]

@@ -126,7 +126,7 @@ int create_common(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* ro
 
   const size_t vsize = store_dtype == DAMN_F64 ? 8 : 4;
   const int64_t pe = padded_entries(nnz);
-  if (hipMalloc(&A->d_rowptr, sizeof(int32_t) * (size_t(nrows) + 1)) != hipSuccess ||
+  if (hipMalloc(&A->d_rowptr, sizeof(int32_t) * (size_t(nrows) + 1 + kRowptrPad)) != hipSuccess ||
       hipMalloc(&A->d_idx, idx_size * pe) != hipSuccess ||
       hipMalloc(&A->d_val, vsize * pe) != hipSuccess) {
     free_mat(A);
@@ -147,7 +147,9 @@ int create_common(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* ro
     });
     src_vals = conv.data();
   }
-  bool ok = hipMemsetAsync(A->d_idx, 0, idx_size * pe, s) == hipSuccess &&
+  bool ok = hipMemsetAsync(A->d_rowptr, 0, sizeof(int32_t) * (size_t(nrows) + 1 + kRowptrPad),
+                           s) == hipSuccess &&
+            hipMemsetAsync(A->d_idx, 0, idx_size * pe, s) == hipSuccess &&
             hipMemsetAsync(A->d_val, 0, vsize * pe, s) == hipSuccess &&
             hipMemcpyAsync(A->d_rowptr, rowptr, sizeof(int32_t) * (size_t(nrows) + 1),
                            hipMemcpyHostToDevice, s) == hipSuccess;

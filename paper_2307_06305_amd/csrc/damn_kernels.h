@@ -7,8 +7,12 @@
 
 namespace damn {
 
-// Rows per stream tile are capped so one workgroup's second step stays short.
-constexpr int32_t kMaxTileRows = 2048;
+// Rows per stream tile are capped so one workgroup's second step stays short
+// and the tile's row pointers fit a fixed LDS area.
+constexpr int32_t kMaxTileRows = 512;
+// Row-pointer arrays are allocated with this many spare (zero) entries so
+// 16-byte copies of a tile's row pointers stay inside the allocation.
+constexpr int32_t kRowptrPad = 16;
 
 struct SpmvArgs {
   int32_t nrows = 0;

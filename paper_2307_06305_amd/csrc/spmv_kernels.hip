@@ -100,6 +100,7 @@ __global__ __launch_bounds__(256) void spmv_stream(
   if (DOT && *done) return;
   V* val_s = reinterpret_cast<V*>(lds);
   I* idx_s = reinterpret_cast<I*>(lds + sizeof(V) * (cap + 16));
+  int32_t* rp_s = reinterpret_cast<int32_t*>(lds + (sizeof(V) + sizeof(I)) * (cap + 16));
 
   const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
   const int32_t r0 = tile_row[t], r1 = tile_row[t + 1];
@@ -128,6 +129,10 @@ __global__ __launch_bounds__(256) void spmv_stream(
   const int32_t a0 = p0 & ~7;
   copy_to_lds(val_s, val, a0, p1 - a0);
   copy_to_lds(idx_s, idx, a0, p1 - a0);
+  // the tile's row pointers rowptr[ar .. r1] (ar = r0 rounded down to 4;
+  // at most kMaxTileRows + 4 entries, padded allocation)
+  const int32_t ar = r0 & ~3;
+  copy_to_lds(rp_s, rowptr, ar, r1 + 1 - ar);
   // the direct-to-LDS writes are tracked by vmcnt; the memory clobber keeps
   // the compiler from moving LDS reads above the wait
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -137,7 +142,7 @@ __global__ __launch_bounds__(256) void spmv_stream(
   const int lane = threadIdx.x % G;
   double dot = 0.0;
   for (int32_t r = r0 + int32_t(threadIdx.x / G); r < r1; r += 256 / G) {
-    const int32_t s = rowptr[r] - a0, e = rowptr[r + 1] - a0;
+    const int32_t s = rp_s[r - ar] - a0, e = rp_s[r + 1 - ar] - a0;
     const V* xs = DA ? x + r : x;
     V acc[4] = {V(0), V(0), V(0), V(0)};
     int32_t k = s + lane;
@@ -293,7 +298,8 @@ hipError_t launch_vector(const SpmvArgs& a, int lanes, int unroll) {
 template <typename I, typename V, bool DA, int G>
 hipError_t launch_stream_g(const SpmvArgs& a) {
   if (a.ntiles == 0) return hipSuccess;
-  const size_t shmem = size_t(a.cap + 16) * (sizeof(I) + sizeof(V));
+  const size_t shmem = size_t(a.cap + 16) * (sizeof(I) + sizeof(V)) +
+                       sizeof(int32_t) * (kMaxTileRows + 16);
   hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G>), dim3(uint32_t(a.ntiles)), dim3(256),
                      shmem, a.stream, a.tile_row, a.rowptr, static_cast<const I*>(a.idx),
                      static_cast<const V*>(a.val), static_cast<const V*>(a.x),
@@ -305,7 +311,8 @@ template <typename I, typename V, bool DA, int G>
 hipError_t launch_stream_dot_g(const SpmvArgs& a, const void* w, double* partial,
                                const int32_t* done) {
   if (a.ntiles == 0) return hipSuccess;
-  const size_t shmem = size_t(a.cap + 16) * (sizeof(I) + sizeof(V));
+  const size_t shmem = size_t(a.cap + 16) * (sizeof(I) + sizeof(V)) +
+                       sizeof(int32_t) * (kMaxTileRows + 16);
   hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, true>), dim3(uint32_t(a.ntiles)), dim3(256),
                      shmem, a.stream, a.tile_row, a.rowptr, static_cast<const I*>(a.idx),
                      static_cast<const V*>(a.val), static_cast<const V*>(a.x),

@@ -186,6 +186,140 @@ def bench_cg(D, args):
     return res
 
 
+SWEEP_N = (16, 24, 32, 48, 64, 80, 96, 112, 128, 160)
+
+
+def graph_time(fn, min_s=0.05, n_epochs=7):
+    """Minimum over epochs of the time per call, with K back-to-back calls of
+    fn captured in one HIP graph (K sized so an epoch lasts about min_s), so
+    that small products are not timed through the Python call overhead."""
+    import torch
+
+    fn()
+    t1 = time_launches(fn, 5)
+    k = max(10, min(2000, int(min_s / max(t1, 1e-7))))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(k):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    best = min(time_launches(g.replay, 1) for _ in range(n_epochs)) / k
+    del g
+    return best, k
+
+
+def graph_autotune(mat, x, y):
+    """The autotuner for products of a few microseconds: every candidate
+    configuration timed through captured graphs; sets and returns the fastest."""
+    from paper_2307_06305_amd.tuning import candidates
+
+    times = {}
+    for c in candidates():
+        mat.set_config(*c)
+        times[c] = graph_time(lambda: mat.apply(x, y), min_s=0.004, n_epochs=3)[0]
+    best = min(times, key=times.get)
+    mat.set_config(*best)
+    return best
+
+
+def bench_sweep(D, args):
+    """DA-CSR against CSR on the 27-point stencil over N^3 grids from 16 to
+    160: relative speed and throughput against the working-set size, with
+    the L2 (4 MB per XCD, 32 MB in all) and MALL (256 MB) boundaries.  No
+    cache flush between products: a set that fits a cache level stays there,
+    as in the paper's Fig. 4."""
+    import torch
+
+    from paper_2307_06305_amd.tuning import autotune, config_name
+    from workloads.matrices import stencil_3d_27pt, uniform_vector
+
+    dev = torch.device("cuda:0")
+    rows = []
+    for N in SWEEP_N:
+        A = stencil_3d_27pt(N, 1001)
+        e = D.encode(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, allow_rcm=False)
+        M = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], e["vals"])
+        Cm = D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals)
+        x = torch.from_numpy(uniform_vector(A.ncols, 2001)).to(dev)
+        y = torch.zeros(A.nrows, dtype=torch.float64, device=dev)
+        T_da = model_bytes(A.nrows, A.ncols, A.nnz, 2)
+        T_csr = model_bytes(A.nrows, A.ncols, A.nnz, 4)
+        row = {"N": N, "n": A.nrows, "nnz": A.nnz, "bandwidth": e["w"],
+               "csr_mb": round(T_csr / 1e6, 2),
+               "regime": "L2" if T_csr <= 32e6 else ("MALL" if T_csr <= 256e6 else "HBM")}
+        for name, mat, T in (("da", M, T_da), ("csr", Cm, T_csr)):
+            mat.apply(x, y)
+            if time_launches(lambda: mat.apply(x, y), 5) < 50e-6:
+                best = graph_autotune(mat, x, y)
+            else:
+                best, _ = autotune(mat, x, y, reps=max(3, args.tune_reps // 2))
+            t, k = graph_time(lambda: mat.apply(x, y))
+            row[name] = {"us": round(t * 1e6, 3), "gbs": round(T / t / 1e9, 1),
+                         "launch": config_name(best), "graph_launches": k}
+        row["speedup"] = round(row["csr"]["us"] / row["da"]["us"], 4)
+        row["predicted_speedup"] = round(T_csr / T_da, 4)
+        log(f"sweep N={N}: {row}")
+        rows.append(row)
+        M.destroy()
+        Cm.destroy()
+        del A, e
+    return rows
+
+
+def bench_cg_cube(D, args):
+    """The 7-point Poisson operator on the 256^3 cube (n 16,777,216): its
+    bandwidth, 65536 in natural order, stays above the 16-bit range after RCM,
+    so the solve runs on int32 CSR, float64 CG against mixed precision with
+    float32-valued CSR inner solves."""
+    import torch
+
+    from paper_2307_06305_amd.tuning import STREAM, autotune, candidates, config_name
+    from workloads import config_vector
+    from workloads.matrices import poisson_3d_7pt
+
+    dev = torch.device("cuda:0")
+    A = poisson_3d_7pt(256, 256, 256)
+    w, _, _, fits = D.fit_check(A.nrows, A.ncols, A.rowptr, A.colids)
+    t0 = time.time()
+    perm = D.rcm(A.nrows, A.rowptr, A.colids)
+    _, w_rcm, fits_rcm = D.refine_bandwidth(A.nrows, A.rowptr, A.colids, perm, max_sweeps=0)
+    t_rcm = time.time() - t0
+    del perm
+    C64 = D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, store=D.F64)
+    C32 = D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, store=D.F32)
+    b = torch.from_numpy(config_vector(3, A.nrows)).to(dev)
+    x64 = torch.zeros_like(b)
+    xm = torch.zeros_like(b)
+    stream_cfgs = [c for c in candidates() if c[0] == STREAM and c[1] <= 16]
+    best64, _ = autotune(C64, b, x64, configs=stream_cfgs, reps=args.tune_reps)
+    b32 = b.float()
+    y32 = torch.zeros_like(b32)
+    best32, _ = autotune(C32, b32, y32, configs=stream_cfgs, reps=args.tune_reps)
+    del b32, y32
+    res = {"workload": "poisson3d_7pt_256^3", "n": A.nrows, "nnz": A.nnz,
+           "bandwidth": w, "fits_int16": bool(fits), "bandwidth_rcm": w_rcm,
+           "fits_int16_rcm": bool(fits_rcm), "rcm_s": round(t_rcm, 2), "index": "int32 CSR",
+           "tol": 1e-10, "launch_f64": config_name(best64), "launch_f32": config_name(best32)}
+    for name, a32, xv in (("fp64", None, x64), ("mixed", C32, xm)):
+        best = None
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = D.cg(C64, b, xv, A32=a32, tol=1e-10, inner_tol=1e-5, max_iter=20000,
+                        check_every=32)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        res[name] = {"s": round(best, 4), **info}
+        log(f"cg cube {name}: {res[name]}")
+    res["speedup_mixed"] = round(res["fp64"]["s"] / res["mixed"]["s"], 3)
+    res["mixed_vs_fp64_rel_err"] = float(((xm - x64).norm() / x64.norm()).item())
+    C64.destroy()
+    C32.destroy()
+    return res
+
+
 def bench_batch(D, args):
     """512 DA-CSR matrices (n log-uniform on [1e3, 2e5]; 2D 5-point, 3D
     7-point, 3D 27-point and random banded; 1-8 right-hand sides): one
@@ -304,6 +438,8 @@ def main():
     ap.add_argument("--skip-banded", action="store_true", help="skip the random banded workload")
     ap.add_argument("--skip-cg", action="store_true", help="skip the conjugate-gradient solves")
     ap.add_argument("--skip-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--skip-sweep", action="store_true", help="skip the 27-point size sweep")
+    ap.add_argument("--skip-cube", action="store_true", help="skip the 256^3 CSR CG solves")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-workgroups", type=int, default=0)
     ap.add_argument("--profile", action="store_true",
@@ -455,6 +591,10 @@ def main():
         res["banded"] = bench_banded(D, args)
     if not args.skip_cg:
         res["cg"] = bench_cg(D, args)
+    if not args.skip_cube:
+        res["cg_cube"] = bench_cg_cube(D, args)
+    if not args.skip_sweep:
+        res["sweep"] = bench_sweep(D, args)
     if not args.skip_batch:
         res["batch"] = bench_batch(D, args)
         res["selector_training"] = bench_selector_training(D, args)

@@ -20,10 +20,11 @@ class BadCSR(ValueError):
 
 
 class NoFit(Exception):
-    """The bandwidth does not fit a 16-bit offset (even after reordering)."""
+    """An index (the bandwidth, or a column) or a value does not fit the
+    storage type asked for (for int16 offsets: even after reordering)."""
 
-    def __init__(self, w):
-        super().__init__(f"bandwidth {w} does not fit int16 (needs w < 32768)")
+    def __init__(self, w, bits=16, what="bandwidth"):
+        super().__init__(f"{what} {w} does not fit int{bits} (needs < {2 ** (bits - 1)})")
         self.w = w
 
 
@@ -162,3 +163,60 @@ def encode(nrows, ncols, rowptr, colids, vals, allow_rcm=True):
         "permuted": True,
         "w": w2,
     }
+
+
+# ---------------------------------------------------------------------------
+# The storage grid of Fig. 3: column indices of 32, 16 or 8 bits and scalars
+# of 64, 32 or 16 bits.  DA formats hold offsets c_i - r_i (Sec. 2), CSR
+# formats absolute columns c_i.
+# ---------------------------------------------------------------------------
+
+# format name -> (index bytes, holds DA offsets)
+INDEX_FORMATS = {"da16": (2, True), "csr32": (4, False), "da8": (1, True), "csr16": (2, False)}
+_INT_TYPES = {1: np.int8, 2: np.int16, 4: np.int32}
+VALUE_TYPES = {"f64": np.float64, "f32": np.float32, "f16": np.float16}
+
+
+def index_limit(nbytes):
+    """A signed index of nbytes holds values of magnitude below 2^(8 nbytes - 1):
+    the rule w < 2^15 of Sec. 2 applied to any width, so the most negative
+    value of the type is never emitted."""
+    return 2 ** (8 * nbytes - 1)
+
+
+def encode_index(fmt, nrows, ncols, rowptr, colids):
+    """Column indices of int32 CSR in format fmt, entry order unchanged.
+
+    DA formats store c_i - r_i and need w below index_limit (Eq. 2); CSR
+    formats store c_i and need every stored column below it (a direct
+    representation with narrower column indices, as the remark closing
+    Sec. 4 counts them).  Raises NoFit otherwise.
+    """
+    nbytes, is_da = INDEX_FORMATS[fmt]
+    check_csr(nrows, ncols, rowptr, colids)
+    lim = index_limit(nbytes)
+    c = np.asarray(colids, dtype=np.int64)
+    if is_da:
+        d = c - entry_rows(nrows, rowptr)
+        w = int(np.abs(d).max()) if d.size else 0
+        if w >= lim:
+            raise NoFit(w, 8 * nbytes)
+        return d.astype(_INT_TYPES[nbytes])
+    m = int(c.max()) if c.size else 0
+    if m >= lim:
+        raise NoFit(m, 8 * nbytes, "column")
+    return c.astype(_INT_TYPES[nbytes])
+
+
+def store_values(vals, vtype):
+    """Values as a matrix of scalar type vtype holds them: IEEE 754 binary64
+    to binary32 / binary16 with round to nearest, ties to even, in one step
+    from the float64 value (never through float32 first).  A finite value
+    that rounds to infinity raises NoFit."""
+    v = np.asarray(vals, dtype=np.float64)
+    with np.errstate(over="ignore"):
+        out = v.astype(VALUE_TYPES[vtype])
+    bad = np.isfinite(v) & ~np.isfinite(out)
+    if np.any(bad):
+        raise NoFit(float(v[bad][0]), 8 * out.itemsize, "value")
+    return out

@@ -320,6 +320,108 @@ def bench_cg_cube(D, args):
     return res
 
 
+def _grid_cell(D, A, fmt, store, x64, tune_reps, graph=False):
+    """Upload A in one storage cell, tune it, time it; model bytes with the
+    cell's index and scalar sizes (x and y float32 unless float64 values)."""
+    import numpy as np
+    import torch
+
+    from paper_2307_06305_amd.tuning import autotune, config_name
+
+    idx, _ = D.encode_index(fmt, A.nrows, A.ncols, A.rowptr, A.colids)
+    M = D.Matrix.create_format(fmt, A.nrows, A.ncols, A.rowptr, idx, A.vals, store=store)
+    del idx
+    f64 = store == D.F64
+    x = torch.from_numpy(x64 if f64 else x64.astype(np.float32)).to("cuda")
+    y = torch.zeros(A.nrows, dtype=torch.float64 if f64 else torch.float32, device="cuda")
+    M.apply(x, y)
+    if graph:
+        best = graph_autotune(M, x, y)
+        t = graph_time(lambda: M.apply(x, y))[0]
+    else:
+        best, _ = autotune(M, x, y, reps=tune_reps)
+        t = epochs(lambda: M.apply(x, y), 30)
+    ib = np.dtype(D.FORMATS[fmt][0]).itemsize
+    sb = np.dtype(D.VALUE_DTYPES[store]).itemsize
+    T = model_bytes(A.nrows, A.ncols, A.nnz, ib, scalar=sb)
+    if store == D.F16:  # x and y are float32: 4 bytes per element, not 2
+        T += 2 * (A.ncols + A.nrows)
+    M.destroy()
+    return {"us": round(t * 1e6, 3), "model_bytes": T, "gbs": round(T / t / 1e9, 1),
+            "launch": config_name(best)}
+
+
+def bench_grid(D, args):
+    """The storage grid of Fig. 3 on the GPU: index widths (int8 / int16 DA
+    offsets, int32 / int16 CSR columns) against scalar widths (float64 /
+    float32 / float16), with the model's predicted speedups; the non-square
+    products of the remark in Sec. 4."""
+    import numpy as np
+
+    from workloads import config_matrix, config_vector, stencil_3d_27pt
+    from workloads.matrices import random_banded, stencil_3d_27pt_box, uniform_vector
+
+    names = {D.FORMAT_DA16: "da16", D.FORMAT_CSR32: "csr32", D.FORMAT_DA8: "da8",
+             D.FORMAT_CSR16: "csr16"}
+    vnames = {D.F64: "f64", D.F32: "f32", D.F16: "f16"}
+    out = {}
+
+    def table(A, x, fmts, graph=False):
+        cells = {}
+        for fmt in fmts:
+            for st in (D.F64, D.F32, D.F16):
+                c = _grid_cell(D, A, fmt, st, x, args.tune_reps, graph)
+                cells[f"{names[fmt]}_{vnames[st]}"] = c
+                log(f"grid {A.name} {names[fmt]} {vnames[st]}: {c}")
+        base = cells[f"{names[fmts[0]]}_f64"]
+        for c in cells.values():
+            c["speedup"] = round(base["us"] / c["us"], 4)
+            c["predicted_speedup"] = round(base["model_bytes"] / c["model_bytes"], 4)
+        return cells
+
+    # 27-point stencil on a 10 x 10 x 20972 box: w = 111 fits int8 offsets
+    A = stencil_3d_27pt_box(10, 10, 20972, 1009)
+    x = uniform_vector(A.ncols, 2009)
+    out["box_10x10x20972"] = {"n": A.nrows, "nnz": A.nnz, "bandwidth": 111,
+                              "cells": table(A, x, [D.FORMAT_CSR32, D.FORMAT_DA16, D.FORMAT_DA8])}
+    del A
+    # the 128^3 stencil: DA16 against CSR32 with each scalar type (the
+    # multi-precision remark after Fig. 3: f64 -> f32 gains 3/2 for CSR32 and
+    # 5/3 for DA16 in the matrix traffic)
+    A = config_matrix(1)
+    x = config_vector(1, A.ncols)
+    cells = table(A, x, [D.FORMAT_CSR32, D.FORMAT_DA16])
+    out["stencil_128^3"] = {"n": A.nrows, "nnz": A.nnz, "cells": cells,
+                            "f64_to_f32": {"csr32": round(cells["csr32_f64"]["us"] / cells["csr32_f32"]["us"], 4),
+                                           "da16": round(cells["da16_f64"]["us"] / cells["da16_f32"]["us"], 4)}}
+    del A
+    # same index width: DA16 against CSR16 (remark closing Sec. 4), on the
+    # largest 27-point cube whose columns fit int16 (32^3 = 32768 rows; its
+    # products sit in L2 and are timed through captured graphs)
+    A = stencil_3d_27pt(32, 1001)
+    x = uniform_vector(A.ncols, 2001)
+    cells = {}
+    for fmt in (D.FORMAT_CSR16, D.FORMAT_DA16):
+        c = _grid_cell(D, A, fmt, D.F64, x, args.tune_reps, graph=True)
+        cells[names[fmt] + "_f64"] = c
+    cells["da16_over_csr16"] = round(cells["csr16_f64"]["us"] / cells["da16_f64"]["us"], 4)
+    out["same_index_width_27pt_32^3"] = cells
+    log(f"grid same index width: {cells}")
+    # non-square (Sec. 4 remark): wide and tall random bands, n = 4M
+    for name, nr, nc in (("wide", 4_000_000, 4_040_000), ("tall", 4_040_000, 4_000_000)):
+        A = random_banded(nr, 1012, half_band=20000, ncols=nc)
+        x = uniform_vector(A.ncols, 2012)
+        res = {"nrows": nr, "ncols": nc, "nnz": A.nnz}
+        for fmt in (D.FORMAT_CSR32, D.FORMAT_DA16):
+            res[names[fmt]] = _grid_cell(D, A, fmt, D.F64, x, args.tune_reps)
+        res["speedup"] = round(res["csr32"]["us"] / res["da16"]["us"], 4)
+        res["predicted_speedup"] = round(res["csr32"]["model_bytes"] / res["da16"]["model_bytes"], 4)
+        out[name] = res
+        log(f"grid {name}: {res}")
+        del A
+    return out
+
+
 def bench_batch(D, args):
     """512 DA-CSR matrices (n log-uniform on [1e3, 2e5]; 2D 5-point, 3D
     7-point, 3D 27-point and random banded; 1-8 right-hand sides): one
@@ -440,6 +542,8 @@ def main():
     ap.add_argument("--skip-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--skip-sweep", action="store_true", help="skip the 27-point size sweep")
     ap.add_argument("--skip-cube", action="store_true", help="skip the 256^3 CSR CG solves")
+    ap.add_argument("--skip-grid", action="store_true",
+                    help="skip the index / scalar width grid and the non-square products")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-workgroups", type=int, default=0)
     ap.add_argument("--profile", action="store_true",
@@ -595,6 +699,8 @@ def main():
         res["cg_cube"] = bench_cg_cube(D, args)
     if not args.skip_sweep:
         res["sweep"] = bench_sweep(D, args)
+    if not args.skip_grid:
+        res["grid"] = bench_grid(D, args)
     if not args.skip_batch:
         res["batch"] = bench_batch(D, args)
         res["selector_training"] = bench_selector_training(D, args)

@@ -50,10 +50,25 @@ typedef enum {
   DAMN_ERR_BREAKDOWN = -8      /* p.Ap <= 0: matrix not positive definite   */
 } damn_status;
 
-typedef enum { DAMN_F64 = 0, DAMN_F32 = 1 } damn_dtype;
+/* Scalar types of stored values (the scalar axis of Fig. 3).  Products
+ * with float16-valued matrices take float32 x and y and accumulate in
+ * float32. */
+typedef enum { DAMN_F64 = 0, DAMN_F32 = 1, DAMN_F16 = 2 } damn_dtype;
 
-/* Column-index kind of a device matrix. */
-typedef enum { DAMN_FORMAT_DA16 = 0, DAMN_FORMAT_CSR32 = 1 } damn_format;
+/* Column-index kind of a device matrix (the index axis of Fig. 3):
+ *   DA16   int16 offsets c - r, needs bandwidth w < 2^15 (Sec. 2)
+ *   CSR32  int32 absolute columns
+ *   DA8    int8 offsets c - r, needs w < 2^7
+ *   CSR16  int16 absolute columns, needs every column < 2^15 (the direct
+ *          narrow-index CSR the remark closing Sec. 4 compares with)
+ * A signed index of b bits holds magnitudes below 2^(b-1): the most
+ * negative value of the type is never used, as for the 16-bit rule. */
+typedef enum {
+  DAMN_FORMAT_DA16 = 0,
+  DAMN_FORMAT_CSR32 = 1,
+  DAMN_FORMAT_DA8 = 2,
+  DAMN_FORMAT_CSR16 = 3
+} damn_format;
 
 /* Opaque device matrix; owns its device arrays. */
 typedef struct damn_mat_s* damn_mat;
@@ -128,6 +143,30 @@ int damn_encode(int32_t nrows, int32_t ncols, const int32_t* rowptr,
                 int32_t* rowptr_out, int16_t* off_out, double* vals_out,
                 int32_t* perm_out, int32_t* permuted, int32_t* w_out);
 
+/* Column indices of int32 CSR in any index format of Fig. 3, entry order
+ * unchanged: DA formats store c - r (Sec. 2, Example 1), CSR formats c.
+ * In:  format (damn_format), host int32 CSR (rowptr[nrows+1],
+ *      colids[nnz]).
+ * Out: idx_out[nnz] of the format's integer type (int8, int16 or int32,
+ *      host, caller-allocated); *w_out = the bandwidth (DA formats) or the
+ *      largest stored column (CSR formats), written on success and on
+ *      DAMN_ERR_NO_FIT.
+ * Errors: DAMN_ERR_NO_FIT (w_out at or above 2^(bits-1); idx_out untouched),
+ *         DAMN_ERR_INVALID_ARG, DAMN_ERR_BAD_CSR. */
+int damn_encode_index(int32_t format, int32_t nrows, int32_t ncols, const int32_t* rowptr,
+                      const int32_t* colids, void* idx_out, int32_t* w_out);
+
+/* Values in a narrower scalar type (the scalar axis of Fig. 3): IEEE 754
+ * round to nearest, ties to even, in one step from the input value (a
+ * float64 value is never rounded to float32 on its way to float16).
+ * In:  n values of vals_dtype (host); dtype no wider than vals_dtype
+ *      (equal types copy).
+ * Out: out[n] of dtype (host, caller-allocated; float16 as its 16 bits).
+ * Errors: DAMN_ERR_NO_FIT (a finite value rounds to infinity; out holds the
+ *         infinities), DAMN_ERR_UNSUPPORTED (widening), DAMN_ERR_INVALID_ARG. */
+int damn_store_values(int64_t n, const void* vals, int32_t vals_dtype, int32_t dtype,
+                      void* out);
+
 /* ------------------------------------------------------------------------
  * Device matrices.
  * --------------------------------------------------------------------- */
@@ -154,6 +193,23 @@ int damn_csr_create(damn_mat* out, int32_t nrows, int32_t ncols,
                     const void* vals, int32_t vals_dtype, int32_t store_dtype,
                     void* stream);
 
+/* Upload a matrix in any cell of the storage grid of Fig. 3.
+ * In:  format (damn_format); host rowptr[nrows+1]; idx[nnz] of the
+ *      format's integer type (as damn_encode_index writes it); vals[nnz] of
+ *      vals_dtype (float64, float32 or float16 bits), stored on the device
+ *      as store_dtype, rounded as damn_store_values does (widening is
+ *      DAMN_ERR_UNSUPPORTED).  Every column (r + off for DA formats) must
+ *      lie in [0, ncols); checked on the host.
+ * Out: *out as for damn_create.  DA handles take damn_spmv, CSR handles
+ *      damn_csr_spmv; x and y are float64 for float64 handles and float32
+ *      otherwise.
+ * Errors: DAMN_ERR_NO_FIT (a value overflows store_dtype),
+ *         DAMN_ERR_INVALID_ARG, DAMN_ERR_BAD_CSR, DAMN_ERR_UNSUPPORTED,
+ *         DAMN_ERR_ALLOC, DAMN_ERR_HIP. */
+int damn_create_format(damn_mat* out, int32_t format, int32_t nrows, int32_t ncols,
+                       const int32_t* rowptr, const void* idx, const void* vals,
+                       int32_t vals_dtype, int32_t store_dtype, void* stream);
+
 /* Release a handle (waits for the device to finish using it). */
 int damn_destroy(damn_mat A);
 
@@ -162,24 +218,26 @@ int damn_mat_info(damn_mat A, int32_t* nrows, int32_t* ncols, int64_t* nnz,
                   int32_t* format, int32_t* dtype);
 
 /* ------------------------------------------------------------------------
- * Products (Sec. 4, Listing 2).  x has ncols entries, y has nrows, both of
- * the matrix's value dtype, in device memory.
+ * Products (Sec. 4, Listing 2).  x has ncols entries, y has nrows, in
+ * device memory: float64 for float64 handles, float32 for float32 and
+ * float16 handles (which accumulate in float32).
  * --------------------------------------------------------------------- */
 
-/* y <- alpha*A*x + beta*y for a DA-CSR handle: row r accumulates
+/* y <- alpha*A*x + beta*y for a DA handle (DA16 or DA8): row r accumulates
  * values[i] * x[r + off[i]] (the shifted-x access of Sec. 4).
  * Errors: DAMN_ERR_INVALID_ARG (null, or a CSR handle), DAMN_ERR_HIP. */
 int damn_spmv(damn_mat A, const void* x, void* y, double alpha, double beta,
               void* stream);
 
-/* Same product for a plain CSR handle (absolute columns). */
+/* Same product for a CSR handle (CSR32 or CSR16, absolute columns). */
 int damn_csr_spmv(damn_mat A, const void* x, void* y, double alpha,
                   double beta, void* stream);
 
 /* Y <- alpha*A*X + beta*Y for nrhs right-hand sides, 1 <= nrhs <= 8.
  * X is ncols x nrhs and Y is nrows x nrhs, both row-major (the nrhs values
- * of one row are adjacent).  Works on DA-CSR and CSR handles.
- * Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_UNSUPPORTED (nrhs > 8). */
+ * of one row are adjacent).  Float64 DA16 and CSR32 handles.
+ * Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_UNSUPPORTED (nrhs > 8, another
+ *         format or scalar type). */
 int damn_spmm(damn_mat A, const void* X, void* Y, int32_t nrhs, double alpha,
               double beta, void* stream);
 
@@ -236,7 +294,7 @@ typedef struct {
 } damn_cg_info;
 
 /* Solve A x = b for symmetric positive definite A, from x0 = 0.
- * A64: float64 handle (DA-CSR or CSR), square.  A32 == NULL: float64 CG
+ * A64: float64 handle (DA16 or CSR32), square.  A32 == NULL: float64 CG
  * (Hestenes-Stiefel; vectors and dot products float64; stops on the
  * recursively updated residual, then reports the true residual).
  * A32 != NULL: mixed precision with iterative refinement.  A32 is the same
@@ -249,8 +307,9 @@ typedef struct {
  * DAMN_ERR_NOT_CONVERGED / DAMN_ERR_BREAKDOWN it holds the last iterate).
  * The call synchronises `stream` (it reads the stop flag every check_every
  * iterations).  Device workspace (about 7 vectors) is kept with A64.
- * Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_NOT_CONVERGED (limits reached),
- *         DAMN_ERR_BREAKDOWN (p.Ap <= 0), DAMN_ERR_ALLOC, DAMN_ERR_HIP. */
+ * Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_UNSUPPORTED (DA8 or CSR16 handles),
+ *         DAMN_ERR_NOT_CONVERGED (limits reached), DAMN_ERR_BREAKDOWN
+ *         (p.Ap <= 0), DAMN_ERR_ALLOC, DAMN_ERR_HIP. */
 int damn_cg(damn_mat A64, damn_mat A32, const double* b, double* x,
             const damn_cg_opts* opts, damn_cg_info* info, void* stream);
 
@@ -269,7 +328,7 @@ typedef struct damn_batch_s* damn_batch;
  * entries (at most 4096) and the tile list is split into `workgroups`
  * contiguous ranges of about equal modelled bytes (0: 1024 workgroups).
  * The launch is captured once into a HIP graph.
- * Errors: DAMN_ERR_INVALID_ARG (null, non-DA or non-float64 handle),
+ * Errors: DAMN_ERR_INVALID_ARG (null, non-DA16 or non-float64 handle),
  *         DAMN_ERR_UNSUPPORTED (nrhs outside 1..8, a row longer than 4096
  *         entries), DAMN_ERR_ALLOC, DAMN_ERR_HIP. */
 int damn_batch_create(damn_batch* out, int32_t count, const damn_mat* mats,

@@ -18,9 +18,14 @@ import numpy as np
 
 from ._lib import DamnError, NoFit, lib, LIB_PATH  # noqa: F401
 
-F64, F32 = 0, 1
-FORMAT_DA16, FORMAT_CSR32 = 0, 1
+F64, F32, F16 = 0, 1, 2
+FORMAT_DA16, FORMAT_CSR32, FORMAT_DA8, FORMAT_CSR16 = 0, 1, 2, 3
 VAR_VECTOR, VAR_STREAM = 0, 1
+
+# the storage grid of Fig. 3: format -> (index dtype, holds DA offsets)
+FORMATS = {FORMAT_DA16: (np.int16, True), FORMAT_CSR32: (np.int32, False),
+           FORMAT_DA8: (np.int8, True), FORMAT_CSR16: (np.int16, False)}
+VALUE_DTYPES = {F64: np.float64, F32: np.float32, F16: np.float16}
 
 _I32P = C.POINTER(C.c_int32)
 
@@ -121,6 +126,43 @@ def encode(nrows, ncols, rowptr, colids, vals, allow_rcm=True):
             "permuted": bool(permuted.value), "w": w.value}
 
 
+def encode_index(fmt, nrows, ncols, rowptr, colids):
+    """Column indices of int32 CSR in format fmt (FORMAT_*), entry order
+    unchanged (host).  Returns (idx, w); raises NoFit (with .w)."""
+    c = _i32(colids)
+    rp = _csr_arrays(nrows, rowptr, c)
+    if fmt not in FORMATS:
+        raise DamnError(-1, "encode_index: unknown format")
+    dt, _ = FORMATS[fmt]
+    idx = np.empty(int(rp[nrows]), dtype=dt)
+    w = C.c_int32()
+    st = lib.damn_encode_index(int(fmt), nrows, ncols, _ptr(rp, C.c_int32), _ptr(c, C.c_int32),
+                               idx.ctypes.data_as(C.c_void_p), C.byref(w))
+    if st == -3:
+        raise NoFit(w.value, "bandwidth" if FORMATS[fmt][1] else "column",
+                    8 * np.dtype(dt).itemsize)
+    _check(st, "encode_index")
+    return idx, w.value
+
+
+def store_values(vals, dtype):
+    """Values rounded to dtype (F64/F32/F16) as the library stores them
+    (host).  Raises NoFit on overflow."""
+    v = np.ascontiguousarray(vals)
+    src = {np.dtype(np.float64): F64, np.dtype(np.float32): F32,
+           np.dtype(np.float16): F16}.get(v.dtype)
+    if src is None:
+        v = v.astype(np.float64)
+        src = F64
+    out = np.empty(v.shape, dtype=VALUE_DTYPES[dtype])
+    st = lib.damn_store_values(v.size, v.ctypes.data_as(C.c_void_p), src, int(dtype),
+                               out.ctypes.data_as(C.c_void_p))
+    if st == -3:
+        raise NoFit(None, bits=8 * out.itemsize)
+    _check(st, "store_values")
+    return out
+
+
 # ---------------------------------------------------------------------------
 # device side
 # ---------------------------------------------------------------------------
@@ -147,7 +189,9 @@ def _dev_ptr(t, dtype, numel, name):
 
 
 class Matrix:
-    """A device matrix (DA-CSR int16 or CSR int32) owned by the library."""
+    """A device matrix in one cell of the storage grid of Fig. 3 (DA-CSR
+    int16 or int8 offsets, CSR int32 or int16 columns; float64, float32 or
+    float16 values) owned by the library."""
 
     def __init__(self, handle, nrows, ncols, nnz, fmt, dtype):
         self._h = handle
@@ -168,6 +212,25 @@ class Matrix:
                                v.ctypes.data_as(C.c_void_p), vd, store, _stream_ptr(stream)),
                "create")
         return cls(h, nrows, ncols, int(rp[nrows]), FORMAT_DA16, store)
+
+    @classmethod
+    def create_format(cls, fmt, nrows, ncols, rowptr, idx, vals, store=F64, stream=None):
+        """Upload any format of the grid: idx as encode_index returns it,
+        vals float64/float32/float16 (rounded to `store` by the library)."""
+        if fmt not in FORMATS:
+            raise DamnError(-1, "create_format: unknown format")
+        ix = np.ascontiguousarray(idx, dtype=FORMATS[fmt][0])
+        v = np.ascontiguousarray(vals)
+        vd = {np.dtype(np.float64): F64, np.dtype(np.float32): F32,
+              np.dtype(np.float16): F16}.get(v.dtype)
+        if vd is None:
+            v, vd = v.astype(np.float64), F64
+        rp = _csr_arrays(nrows, rowptr, ix, v)
+        h = C.c_void_p()
+        _check(lib.damn_create_format(C.byref(h), int(fmt), nrows, ncols, _ptr(rp, C.c_int32),
+                                      ix.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p),
+                                      vd, int(store), _stream_ptr(stream)), "create_format")
+        return cls(h, nrows, ncols, int(rp[nrows]), fmt, store)
 
     @classmethod
     def csr_create(cls, nrows, ncols, rowptr, colids, vals, store=F64, stream=None):
@@ -219,9 +282,13 @@ class Matrix:
                                  _dev_ptr(y, dt, self.nrows, "y"), float(alpha), float(beta),
                                  _stream_ptr(stream)), "csr_spmv")
 
+    @property
+    def is_da(self):
+        return FORMATS[self.format][1]
+
     def apply(self, x, y, alpha=1.0, beta=0.0, stream=None):
         """spmv or csr_spmv, whichever matches the handle's format."""
-        f = self.spmv if self.format == FORMAT_DA16 else self.csr_spmv
+        f = self.spmv if self.is_da else self.csr_spmv
         f(x, y, alpha, beta, stream)
 
     def spmm(self, X, Y, alpha=1.0, beta=0.0, stream=None):

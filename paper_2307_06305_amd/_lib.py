@@ -19,10 +19,15 @@ class DamnError(RuntimeError):
 
 
 class NoFit(Exception):
-    """Bandwidth >= 2^15, also after reordering; .w is the best bandwidth found."""
+    """An index or value does not fit its storage type: for 16-bit DA
+    offsets, bandwidth >= 2^15 also after reordering.  .w is the bandwidth
+    (or largest column) found, None for a value overflow."""
 
-    def __init__(self, w):
-        super().__init__(f"bandwidth {w} does not fit a 16-bit offset")
+    def __init__(self, w, what="bandwidth", bits=16):
+        if w is None:
+            super().__init__(f"a value overflows float{bits}")
+        else:
+            super().__init__(f"{what} {w} does not fit a {bits}-bit index")
         self.w = w
 
 
@@ -55,6 +60,10 @@ _SIGS = {
     "damn_create": (C.c_int, [C.POINTER(_vp), _i32, _i32, _pi32, _pi16, _vp, _i32, _i32, _vp]),
     "damn_csr_create": (C.c_int, [C.POINTER(_vp), _i32, _i32, _pi32, _pi32, _vp, _i32, _i32,
                                   _vp]),
+    "damn_encode_index": (C.c_int, [_i32, _i32, _i32, _pi32, _pi32, _vp, _pi32]),
+    "damn_store_values": (C.c_int, [_i64, _vp, _i32, _i32, _vp]),
+    "damn_create_format": (C.c_int, [C.POINTER(_vp), _i32, _i32, _i32, _pi32, _vp, _vp, _i32,
+                                     _i32, _vp]),
     "damn_destroy": (C.c_int, [_vp]),
     "damn_mat_info": (C.c_int, [_vp, _pi32, _pi32, _pi64, _pi32, _pi32]),
     "damn_spmv": (C.c_int, [_vp, _vp, _vp, _f64, _f64, _vp]),

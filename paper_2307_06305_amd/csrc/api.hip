@@ -63,7 +63,9 @@ int host_threads() {
 
 namespace {
 
-inline int64_t padded_entries(int64_t nnz) { return ((nnz + 7) / 8) * 8 + 16; }
+// Entry arrays are padded (and zero-filled) so the stream variant's 16-byte
+// pieces, which may run up to 15 entries past the last one, stay inside.
+inline int64_t padded_entries(int64_t nnz) { return ((nnz + 15) / 16) * 16 + 32; }
 
 // Default launch shape: the stream variant with 2048-entry tiles; one lane
 // per row for very short rows, two otherwise, and more lanes for long rows
@@ -96,14 +98,15 @@ void free_mat(damn_mat A) {
   delete A;
 }
 
+// Upload a validated matrix: indices of `format` as given, values rounded
+// from vals_dtype to store_dtype (damn_store_values).
 int create_common(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* rowptr,
-                  const void* idx, size_t idx_size, const void* vals, int32_t vals_dtype,
-                  int32_t store_dtype, void* stream, int32_t format) {
+                  const void* idx, const void* vals, int32_t vals_dtype, int32_t store_dtype,
+                  void* stream, int32_t format) {
   if (out == nullptr || rowptr == nullptr) return DAMN_ERR_INVALID_ARG;
-  if ((vals_dtype != DAMN_F64 && vals_dtype != DAMN_F32) ||
-      (store_dtype != DAMN_F64 && store_dtype != DAMN_F32))
-    return DAMN_ERR_INVALID_ARG;
-  if (store_dtype == DAMN_F64 && vals_dtype == DAMN_F32) return DAMN_ERR_UNSUPPORTED;
+  if (value_bytes(vals_dtype) == 0 || value_bytes(store_dtype) == 0) return DAMN_ERR_INVALID_ARG;
+  if (value_bytes(store_dtype) > value_bytes(vals_dtype)) return DAMN_ERR_UNSUPPORTED;
+  const size_t idx_size = size_t(index_bytes(format));
   const int64_t nnz = rowptr[nrows];
   if (nnz > 0 && (idx == nullptr || vals == nullptr)) return DAMN_ERR_INVALID_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -124,7 +127,7 @@ int create_common(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* ro
   A->dtype = store_dtype;
   A->cfg = default_config(nrows, nnz);
 
-  const size_t vsize = store_dtype == DAMN_F64 ? 8 : 4;
+  const size_t vsize = size_t(value_bytes(store_dtype));
   const int64_t pe = padded_entries(nnz);
   if (hipMalloc(&A->d_rowptr, sizeof(int32_t) * (size_t(nrows) + 1 + kRowptrPad)) != hipSuccess ||
       hipMalloc(&A->d_idx, idx_size * pe) != hipSuccess ||
@@ -132,19 +135,20 @@ int create_common(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* ro
     free_mat(A);
     return DAMN_ERR_ALLOC;
   }
-  std::vector<float> conv;
+  std::vector<unsigned char> conv;
   const void* src_vals = vals;
-  if (store_dtype == DAMN_F32 && vals_dtype == DAMN_F64) {
+  if (store_dtype != vals_dtype) {
     try {
-      conv.resize(size_t(nnz));
+      conv.resize(size_t(nnz) * vsize);
     } catch (const std::bad_alloc&) {
       free_mat(A);
       return DAMN_ERR_ALLOC;
     }
-    const double* v = static_cast<const double*>(vals);
-    parallel_for(nnz, [&](int64_t b, int64_t e) {
-      for (int64_t i = b; i < e; ++i) conv[i] = float(v[i]);  // round to nearest even
-    });
+    const int st = damn_store_values(nnz, vals, vals_dtype, store_dtype, conv.data());
+    if (st != DAMN_OK) {
+      free_mat(A);
+      return st;
+    }
     src_vals = conv.data();
   }
   bool ok = hipMemsetAsync(A->d_rowptr, 0, sizeof(int32_t) * (size_t(nrows) + 1 + kRowptrPad),
@@ -167,8 +171,8 @@ int create_common(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* ro
 }
 
 int run_spmv(damn_mat A, const void* x, void* y, double alpha, double beta, void* stream,
-             int32_t want_format) {
-  if (A == nullptr || A->format != want_format) return DAMN_ERR_INVALID_ARG;
+             bool want_da) {
+  if (A == nullptr || format_is_da(A->format) != want_da) return DAMN_ERR_INVALID_ARG;
   if ((x == nullptr && A->ncols > 0 && alpha != 0.0) || (y == nullptr && A->nrows > 0))
     return DAMN_ERR_INVALID_ARG;
   SpmvArgs a;
@@ -182,8 +186,8 @@ int run_spmv(damn_mat A, const void* x, void* y, double alpha, double beta, void
   a.alpha = alpha;
   a.beta = beta;
   a.read_y = beta != 0.0;
-  a.da = A->format == DAMN_FORMAT_DA16;
-  a.f32 = A->dtype == DAMN_F32;
+  a.format = A->format;
+  a.store = A->dtype;
   a.stream = static_cast<hipStream_t>(stream);
   if (A->cfg.variant == DAMN_VAR_STREAM) {
     const int st = build_tiles(A, A->cfg.tile);
@@ -208,7 +212,9 @@ const char* damn_status_string(int status) {
     case DAMN_OK: return "ok";
     case DAMN_ERR_INVALID_ARG: return "invalid argument";
     case DAMN_ERR_BAD_CSR: return "malformed CSR structure";
-    case DAMN_ERR_NO_FIT: return "bandwidth does not fit a 16-bit offset";
+    case DAMN_ERR_NO_FIT:
+      return "index or value does not fit its storage type (16-bit offsets need bandwidth "
+             "< 2^15)";
     case DAMN_ERR_HIP: return "HIP runtime error";
     case DAMN_ERR_ALLOC: return "allocation failed";
     case DAMN_ERR_UNSUPPORTED: return "unsupported combination";
@@ -241,8 +247,8 @@ int damn_create(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* rowp
     if (local) __atomic_store_n(&bad, 1, __ATOMIC_RELAXED);
   }, 4096);
   if (bad) return DAMN_ERR_BAD_CSR;
-  return create_common(out, nrows, ncols, rowptr, off, sizeof(int16_t), vals, vals_dtype,
-                       store_dtype, stream, DAMN_FORMAT_DA16);
+  return create_common(out, nrows, ncols, rowptr, off, vals, vals_dtype, store_dtype, stream,
+                       DAMN_FORMAT_DA16);
 }
 
 int damn_csr_create(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* rowptr,
@@ -250,8 +256,38 @@ int damn_csr_create(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* 
                     int32_t store_dtype, void* stream) {
   const int st = check_csr(nrows, ncols, rowptr, colids);
   if (st != DAMN_OK) return st;
-  return create_common(out, nrows, ncols, rowptr, colids, sizeof(int32_t), vals, vals_dtype,
-                       store_dtype, stream, DAMN_FORMAT_CSR32);
+  return create_common(out, nrows, ncols, rowptr, colids, vals, vals_dtype, store_dtype, stream,
+                       DAMN_FORMAT_CSR32);
+}
+
+int damn_create_format(damn_mat* out, int32_t format, int32_t nrows, int32_t ncols,
+                       const int32_t* rowptr, const void* idx, const void* vals,
+                       int32_t vals_dtype, int32_t store_dtype, void* stream) {
+  const int ib = index_bytes(format);
+  if (ib == 0 || nrows < 0 || ncols < 0 || rowptr == nullptr) return DAMN_ERR_INVALID_ARG;
+  if (rowptr[0] != 0) return DAMN_ERR_BAD_CSR;
+  for (int32_t r = 0; r < nrows; ++r)
+    if (rowptr[r + 1] < rowptr[r]) return DAMN_ERR_BAD_CSR;
+  const int64_t nnz = rowptr[nrows];
+  if (nnz > 0 && (idx == nullptr || vals == nullptr)) return DAMN_ERR_INVALID_ARG;
+  // every column (r + off for DA) inside [0, ncols), so no kernel reads outside x
+  const bool da = format_is_da(format);
+  int32_t bad = 0;
+  parallel_for(nrows, [&](int64_t b, int64_t e) {
+    int32_t local = 0;
+    for (int64_t r = b; r < e; ++r)
+      for (int64_t i = rowptr[r]; i < rowptr[r + 1]; ++i) {
+        const int64_t v = ib == 1   ? int64_t(static_cast<const int8_t*>(idx)[i])
+                          : ib == 2 ? int64_t(static_cast<const int16_t*>(idx)[i])
+                                    : int64_t(static_cast<const int32_t*>(idx)[i]);
+        const int64_t c = da ? r + v : v;
+        local |= (c < 0) | (c >= ncols);
+      }
+    if (local) __atomic_store_n(&bad, 1, __ATOMIC_RELAXED);
+  }, 4096);
+  if (bad) return DAMN_ERR_BAD_CSR;
+  return create_common(out, nrows, ncols, rowptr, idx, vals, vals_dtype, store_dtype, stream,
+                       format);
 }
 
 int damn_destroy(damn_mat A) {
@@ -277,19 +313,20 @@ int damn_mat_info(damn_mat A, int32_t* nrows, int32_t* ncols, int64_t* nnz, int3
 }
 
 int damn_spmv(damn_mat A, const void* x, void* y, double alpha, double beta, void* stream) {
-  return run_spmv(A, x, y, alpha, beta, stream, DAMN_FORMAT_DA16);
+  return run_spmv(A, x, y, alpha, beta, stream, true);
 }
 
 int damn_csr_spmv(damn_mat A, const void* x, void* y, double alpha, double beta,
                   void* stream) {
-  return run_spmv(A, x, y, alpha, beta, stream, DAMN_FORMAT_CSR32);
+  return run_spmv(A, x, y, alpha, beta, stream, false);
 }
 
 int damn_spmm(damn_mat A, const void* X, void* Y, int32_t nrhs, double alpha, double beta,
               void* stream) {
   if (A == nullptr || nrhs < 1) return DAMN_ERR_INVALID_ARG;
   if (nrhs > 8) return DAMN_ERR_UNSUPPORTED;
-  if (A->dtype != DAMN_F64) return DAMN_ERR_UNSUPPORTED;
+  if (A->dtype != DAMN_F64 || (A->format != DAMN_FORMAT_DA16 && A->format != DAMN_FORMAT_CSR32))
+    return DAMN_ERR_UNSUPPORTED;
   if ((X == nullptr && A->ncols > 0 && alpha != 0.0) || (Y == nullptr && A->nrows > 0))
     return DAMN_ERR_INVALID_ARG;
   SpmvArgs a;
@@ -303,7 +340,8 @@ int damn_spmm(damn_mat A, const void* X, void* Y, int32_t nrhs, double alpha, do
   a.alpha = alpha;
   a.beta = beta;
   a.read_y = beta != 0.0;
-  a.da = A->format == DAMN_FORMAT_DA16;
+  a.format = A->format;
+  a.store = A->dtype;
   a.stream = static_cast<hipStream_t>(stream);
   const hipError_t e = launch_spmm(a, A->cfg.lanes, nrhs);
   return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;

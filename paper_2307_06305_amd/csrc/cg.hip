@@ -327,8 +327,8 @@ SpmvArgs stream_args(damn_mat A, const void* x, void* y, double alpha, double be
   a.alpha = alpha;
   a.beta = beta;
   a.read_y = beta != 0.0;
-  a.da = A->format == DAMN_FORMAT_DA16;
-  a.f32 = A->dtype == DAMN_F32;
+  a.format = A->format;
+  a.store = A->dtype;
   a.tile_row = A->d_tiles;
   a.ntiles = A->ntiles;
   a.cap = A->tiles_cap;
@@ -407,6 +407,8 @@ extern "C" int damn_cg(damn_mat A64, damn_mat A32, const double* b, double* x,
   if (A64 == nullptr || opts == nullptr || info == nullptr) return DAMN_ERR_INVALID_ARG;
   if (A64->nrows != A64->ncols || A64->dtype != DAMN_F64) return DAMN_ERR_INVALID_ARG;
   if (A64->nrows > 0 && (b == nullptr || x == nullptr)) return DAMN_ERR_INVALID_ARG;
+  if (A64->format != DAMN_FORMAT_DA16 && A64->format != DAMN_FORMAT_CSR32)
+    return DAMN_ERR_UNSUPPORTED;
   // the vector kernels move 16-byte packs
   if ((reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(x)) & 15)
     return DAMN_ERR_INVALID_ARG;

@@ -33,8 +33,9 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kNonTemporal = 2;  // cache-policy bit "nt" of gfx950 loads
 
-// Issue direct-to-LDS copies of elements [a0, a0 + n) of src (a0 a multiple
-// of 8) into dst[0, ...), 16 bytes per lane.  Lane l of wave w copies piece
+// Issue direct-to-LDS copies of elements [a0, a0 + n) of src (src + a0
+// 16-byte aligned) into dst[0, ...), 16 bytes per lane; the last piece may
+// run up to 16 bytes past the range.  Lane l of wave w copies piece
 // 64*(w + 4*j) + l; every wave writes 1 KiB contiguous blocks of LDS.
 template <typename T>
 __device__ __forceinline__ void copy_to_lds(T* __restrict__ dst, const T* __restrict__ src,

@@ -44,4 +44,11 @@ int refine_bandwidth(int32_t n, const int32_t* rowptr, const int32_t* colids, in
                      int32_t max_sweeps, int64_t limit, int64_t* w_out);
 constexpr int32_t kRefineSweeps = 32;
 
+// The storage grid of Fig. 3 (host_grid.cpp): bytes of a format's index and
+// of a scalar type (0 for an unknown enum value), and whether a format holds
+// DA offsets.
+int index_bytes(int32_t format);
+bool format_is_da(int32_t format);
+int value_bytes(int32_t dtype);
+
 }  // namespace damn

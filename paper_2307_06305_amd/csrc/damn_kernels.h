@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "damn.h"
+
 namespace damn {
 
 // Rows per stream tile are capped so one workgroup's second step stays short
@@ -18,15 +20,15 @@ struct SpmvArgs {
   int32_t nrows = 0;
   int32_t ncols = 0;
   const int32_t* rowptr = nullptr;
-  const void* idx = nullptr;  // int16 offsets (da) or int32 columns
-  const void* val = nullptr;  // float64 or float32 (f32)
+  const void* idx = nullptr;  // indices of `format` (damn_format)
+  const void* val = nullptr;  // values of `store` (damn_dtype)
   const void* x = nullptr;
   void* y = nullptr;
   double alpha = 1.0;
   double beta = 0.0;
   int32_t read_y = 0;  // beta != 0
-  bool da = true;
-  bool f32 = false;
+  int32_t format = DAMN_FORMAT_DA16;
+  int32_t store = DAMN_F64;  // x, y and sums are float64 for DAMN_F64, else float32
   // stream variant
   const int32_t* tile_row = nullptr;
   int64_t ntiles = 0;
@@ -36,12 +38,14 @@ struct SpmvArgs {
 
 // variant 0 = vector (lanes, unroll), 1 = stream (lanes = G, tiles in args)
 hipError_t launch_spmv(const SpmvArgs& a, int variant, int lanes, int unroll);
+// The same for 8-bit DA, 16-bit CSR and float16 values (spmv_grid.hip).
+hipError_t launch_spmv_grid(const SpmvArgs& a, int variant, int lanes, int unroll);
 // Stream variant with the conjugate-gradient epilogue: partial[t] = sum of
 // y_r * w_r over tile t (w = nullptr: w = y), skipped entirely when *done.
-// lanes in {1, 2, 4, 8, 16}; alpha != 0.
+// lanes in {1, 2, 4, 8, 16}; alpha != 0; DA16 or CSR32, float64 or float32.
 hipError_t launch_spmv_dot(const SpmvArgs& a, int lanes, const void* w, double* partial,
                            const int32_t* done);
-// float64 only; 1 <= nrhs <= 8
+// float64 DA16 or CSR32 only; 1 <= nrhs <= 8
 hipError_t launch_spmm(const SpmvArgs& a, int lanes, int nrhs);
 hipError_t launch_stream_read(const void* src, int64_t bytes, double* sink, hipStream_t s);
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);

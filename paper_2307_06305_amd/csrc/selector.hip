@@ -354,8 +354,9 @@ int damn_autotune(damn_mat A, int32_t nrhs, const void* X, void* Y, int32_t reps
     if (st != DAMN_OK) break;
     auto once = [&]() {
       if (nrhs > 1) return damn_spmm(A, X, Y, nrhs, 1.0, 0.0, stream);
-      return A->format == DAMN_FORMAT_DA16 ? damn_spmv(A, X, Y, 1.0, 0.0, stream)
-                                           : damn_csr_spmv(A, X, Y, 1.0, 0.0, stream);
+      return A->format == DAMN_FORMAT_DA16 || A->format == DAMN_FORMAT_DA8
+                 ? damn_spmv(A, X, Y, 1.0, 0.0, stream)
+                 : damn_csr_spmv(A, X, Y, 1.0, 0.0, stream);
     };
     st = once();  // warm
     if (st != DAMN_OK) break;

@@ -1,0 +1,303 @@
+// Product kernels y <- alpha*A*x + beta*y (Sec. 4) as templates over the
+// storage grid of Fig. 3, and their launchers.  Instantiated by
+// spmv_kernels.hip (16-bit DA offsets and 32-bit CSR columns with float64 and
+// float32 values) and spmv_grid.hip (the other cells).
+//
+// Template arguments: I is the stored index type (int8/int16 offsets c - r
+// for DA, int16/int32 columns for CSR), S the stored value type (double,
+// float or _Float16), V the arithmetic type of x, y and the sums (double for
+// double values, float otherwise).
+//
+// DA rows use the shifted vector xs = x + row, so entry i of row r reads
+// xs[off[i]] = x[r + off[i]] (the per-row pointer shift of Sec. 4; one add
+// per row instead of one per entry).  For a tall matrix xs may point outside
+// x, but every dereference lands inside it (Sec. 4, remark on non-square
+// matrices); the host checks every column against [0, ncols) when a matrix
+// is uploaded, so no kernel reads outside x.
+//
+// SpMV is bound by HBM bandwidth (Eq. 1, Eq. 3): 2 flops per 10 bytes of
+// DA-CSR float64 matrix data.  The kernels therefore care about coalesced
+// streaming of indices and values, about keeping x in L2, and about filling
+// all 256 CUs; no matrix cores are involved.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "damn_device.h"
+#include "damn_kernels.h"
+
+namespace damn {
+namespace kern {
+
+// ---------------------------------------------------------------------------
+// Vector variant: LANES lanes of a wavefront per row (LANES = 1: one row per
+// lane), UNROLL independent partial sums per lane.  One workgroup of 256
+// threads covers 256/LANES consecutive rows.
+// ---------------------------------------------------------------------------
+template <typename I, typename V, bool DA, int LANES, int UNROLL, typename S = V>
+__global__ __launch_bounds__(256) void spmv_vector(
+    int32_t nrows, const int32_t* __restrict__ rowptr, const I* __restrict__ idx,
+    const S* __restrict__ val, const V* __restrict__ x, V* __restrict__ y, V alpha,
+    V beta, int32_t read_y) {
+  constexpr int RPB = 256 / LANES;
+  const uint32_t b = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int64_t row = int64_t(b) * RPB + threadIdx.x / LANES;
+  const int lane = threadIdx.x % LANES;
+  if (row >= nrows) return;  // a row's LANES lanes leave together
+  const int32_t p0 = rowptr[row], p1 = rowptr[row + 1];
+  const V* xs = DA ? x + row : x;
+  V acc[UNROLL];
+#pragma unroll
+  for (int u = 0; u < UNROLL; ++u) acc[u] = V(0);
+  int32_t p = p0 + lane;
+  for (; p + (UNROLL - 1) * LANES < p1; p += UNROLL * LANES) {
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const int32_t q = p + u * LANES;
+      acc[u] += V(val[q]) * xs[idx[q]];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < UNROLL - 1; ++u) {
+    const int32_t q = p + u * LANES;
+    if (q < p1) acc[u] += V(val[q]) * xs[idx[q]];
+  }
+  V s = acc[0];
+#pragma unroll
+  for (int u = 1; u < UNROLL; ++u) s += acc[u];
+  if (LANES > 1) s = group_sum(s, LANES);
+  if (lane == 0) y[row] = finish(s, alpha, beta, read_y != 0, y + row);
+}
+
+// ---------------------------------------------------------------------------
+// Stream variant.  The host cuts the rows into tiles of consecutive rows
+// holding at most `cap` entries (and at most kMaxTileRows rows); a row longer
+// than `cap` is a tile of its own.  A workgroup:
+//   1. copies the tile's indices, values and row pointers from HBM straight
+//      into LDS with 16-byte direct-to-LDS loads (global_load_lds_dwordx4),
+//      starting at the tile's first entry rounded down so every 16-byte piece
+//      is aligned.  The entry loads carry the non-temporal hint: the matrix is
+//      read once, and keeping it from displacing x in L2 means each x line is
+//      fetched from HBM once;
+//   2. reduces each row from LDS with G lanes per row, gathering x.
+// Step 1 streams at full load width whatever the row lengths; step 2 puts
+// neighbouring rows on neighbouring lanes, so for banded matrices the x
+// gathers of one instruction hit few cache lines.
+// ---------------------------------------------------------------------------
+
+// LDS layout of one tile: indices and values of up to `cap` entries plus the
+// alignment slack, then the row pointers.
+template <typename I, typename S>
+struct TileLds {
+  // the copied range starts at the tile's first entry rounded down to kAlign
+  // entries, so 16-byte pieces of both arrays start on 16-byte boundaries
+  static constexpr int32_t kAlign =
+      int32_t(16 / sizeof(I) > 16 / sizeof(S) ? 16 / sizeof(I) : 16 / sizeof(S));
+  // entries per array: cap + (kAlign - 1) slack + up to one partial piece
+  // (at most cap + 30), rounded to 16 so every array starts 16-byte aligned
+  __host__ __device__ static constexpr int32_t slots(int32_t cap) { return (cap + 32 + 15) & ~15; }
+  static constexpr size_t bytes(int32_t cap) {
+    return size_t(slots(cap)) * (sizeof(I) + sizeof(S)) + sizeof(int32_t) * (kMaxTileRows + 16);
+  }
+};
+
+// Workgroup sum of one double per thread, in a fixed order (wave sums, then
+// the four wave results left to right); the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* scratch4) {
+  v = group_sum(v, 64);
+  if ((threadIdx.x & 63) == 0) scratch4[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (scratch4[0] + scratch4[1]) + (scratch4[2] + scratch4[3]);
+}
+
+// Optional epilogue for conjugate gradients (DOT): each workgroup also writes
+// partial[t] = sum over its rows of y_r * w_r in float64 (w = nullptr means
+// w = y), and every workgroup returns at once when *done is nonzero.
+template <typename I, typename V, bool DA, int G, bool DOT = false, typename S = V>
+__global__ __launch_bounds__(256) void spmv_stream(
+    const int32_t* __restrict__ tile_row, const int32_t* __restrict__ rowptr,
+    const I* __restrict__ idx, const S* __restrict__ val, const V* __restrict__ x,
+    V* __restrict__ y, V alpha, V beta, int32_t read_y, int32_t cap,
+    const V* __restrict__ w = nullptr, double* __restrict__ partial = nullptr,
+    const int32_t* __restrict__ done = nullptr) {
+  using L = TileLds<I, S>;
+  extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ double red[4];
+  if (DOT && *done) return;
+  const int32_t slots = L::slots(cap);
+  S* val_s = reinterpret_cast<S*>(lds);
+  I* idx_s = reinterpret_cast<I*>(lds + sizeof(S) * slots);
+  int32_t* rp_s = reinterpret_cast<int32_t*>(lds + (sizeof(S) + sizeof(I)) * slots);
+
+  const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int32_t r0 = tile_row[t], r1 = tile_row[t + 1];
+  const int32_t p0 = rowptr[r0], p1 = rowptr[r1];
+
+  if (p1 - p0 > cap) {
+    // one long row: the whole workgroup strides over it
+    __shared__ V part[4];
+    const V* xs = DA ? x + r0 : x;
+    V acc = V(0);
+    for (int32_t q = p0 + threadIdx.x; q < p1; q += 256) acc += V(val[q]) * xs[idx[q]];
+    acc = group_sum(acc, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const V s = (part[0] + part[1]) + (part[2] + part[3]);
+      const V yr = finish(s, alpha, beta, read_y != 0, y + r0);
+      y[r0] = yr;
+      if (DOT) partial[t] = double(yr) * double(w ? w[r0] : yr);
+    }
+    return;
+  }
+
+  // 1. entries [a0, p1) into LDS (a0 = p0 rounded down to kAlign; the copies
+  //    stay within slots entries), and the row pointers rowptr[ar .. r1]
+  //    (ar = r0 rounded down to 4; at most kMaxTileRows + 4 entries, from an
+  //    allocation padded for the last piece)
+  const int32_t a0 = p0 & ~(L::kAlign - 1);
+  copy_to_lds(val_s, val, a0, p1 - a0);
+  copy_to_lds(idx_s, idx, a0, p1 - a0);
+  const int32_t ar = r0 & ~3;
+  copy_to_lds(rp_s, rowptr, ar, r1 + 1 - ar);
+  // the direct-to-LDS writes are tracked by vmcnt; the memory clobber keeps
+  // the compiler from moving LDS reads above the wait
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+
+  // 2. G lanes per row
+  const int lane = threadIdx.x % G;
+  double dot = 0.0;
+  for (int32_t r = r0 + int32_t(threadIdx.x / G); r < r1; r += 256 / G) {
+    const int32_t s = rp_s[r - ar] - a0, e = rp_s[r + 1 - ar] - a0;
+    const V* xs = DA ? x + r : x;
+    V acc[4] = {V(0), V(0), V(0), V(0)};
+    int32_t k = s + lane;
+    for (; k + 3 * G < e; k += 4 * G) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += V(val_s[k + u * G]) * xs[idx_s[k + u * G]];
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+      if (k + u * G < e) acc[u] += V(val_s[k + u * G]) * xs[idx_s[k + u * G]];
+    V sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    if (G > 1) sum = group_sum(sum, G);
+    if (lane == 0) {
+      const V yr = finish(sum, alpha, beta, read_y != 0, y + r);
+      y[r] = yr;
+      if (DOT) dot += double(yr) * double(w ? w[r] : yr);
+    }
+  }
+  if (DOT) {
+    dot = block_sum(dot, red);
+    if (threadIdx.x == 0) partial[t] = dot;
+  }
+}
+
+}  // namespace kern
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+namespace launch {
+
+template <typename I, typename S, typename V, bool DA, int LANES>
+hipError_t vector_u(const SpmvArgs& a, int unroll) {
+  const int rpb = 256 / LANES;
+  const uint32_t blocks = uint32_t((int64_t(a.nrows) + rpb - 1) / rpb);
+  if (blocks == 0) return hipSuccess;
+  const I* idx = static_cast<const I*>(a.idx);
+  const S* val = static_cast<const S*>(a.val);
+  const V* x = static_cast<const V*>(a.x);
+  V* y = static_cast<V*>(a.y);
+  switch (unroll) {
+    case 1:
+      hipLaunchKernelGGL((kern::spmv_vector<I, V, DA, LANES, 1, S>), dim3(blocks), dim3(256), 0,
+                         a.stream, a.nrows, a.rowptr, idx, val, x, y, V(a.alpha), V(a.beta),
+                         a.read_y);
+      break;
+    case 2:
+      hipLaunchKernelGGL((kern::spmv_vector<I, V, DA, LANES, 2, S>), dim3(blocks), dim3(256), 0,
+                         a.stream, a.nrows, a.rowptr, idx, val, x, y, V(a.alpha), V(a.beta),
+                         a.read_y);
+      break;
+    default:
+      hipLaunchKernelGGL((kern::spmv_vector<I, V, DA, LANES, 4, S>), dim3(blocks), dim3(256), 0,
+                         a.stream, a.nrows, a.rowptr, idx, val, x, y, V(a.alpha), V(a.beta),
+                         a.read_y);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <typename I, typename S, typename V, bool DA>
+hipError_t vector(const SpmvArgs& a, int lanes, int unroll) {
+  switch (lanes) {
+    case 1: return vector_u<I, S, V, DA, 1>(a, unroll);
+    case 2: return vector_u<I, S, V, DA, 2>(a, unroll);
+    case 4: return vector_u<I, S, V, DA, 4>(a, unroll);
+    case 8: return vector_u<I, S, V, DA, 8>(a, unroll);
+    case 16: return vector_u<I, S, V, DA, 16>(a, unroll);
+    case 32: return vector_u<I, S, V, DA, 32>(a, unroll);
+    default: return vector_u<I, S, V, DA, 64>(a, unroll);
+  }
+}
+
+template <typename I, typename S, typename V, bool DA, int G>
+hipError_t stream_g(const SpmvArgs& a) {
+  if (a.ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, false, S>), dim3(uint32_t(a.ntiles)),
+                     dim3(256), (kern::TileLds<I, S>::bytes(a.cap)), a.stream, a.tile_row,
+                     a.rowptr, static_cast<const I*>(a.idx), static_cast<const S*>(a.val),
+                     static_cast<const V*>(a.x), static_cast<V*>(a.y), V(a.alpha), V(a.beta),
+                     a.read_y, a.cap, nullptr, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+template <typename I, typename S, typename V, bool DA>
+hipError_t stream(const SpmvArgs& a, int lanes) {
+  switch (lanes) {
+    case 1: return stream_g<I, S, V, DA, 1>(a);
+    case 2: return stream_g<I, S, V, DA, 2>(a);
+    case 4: return stream_g<I, S, V, DA, 4>(a);
+    case 8: return stream_g<I, S, V, DA, 8>(a);
+    case 16: return stream_g<I, S, V, DA, 16>(a);
+    case 32: return stream_g<I, S, V, DA, 32>(a);
+    default: return stream_g<I, S, V, DA, 64>(a);
+  }
+}
+
+template <typename I, typename V, bool DA, int G>
+hipError_t stream_dot_g(const SpmvArgs& a, const void* w, double* partial, const int32_t* done) {
+  if (a.ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, true, V>), dim3(uint32_t(a.ntiles)),
+                     dim3(256), (kern::TileLds<I, V>::bytes(a.cap)), a.stream, a.tile_row,
+                     a.rowptr, static_cast<const I*>(a.idx), static_cast<const V*>(a.val),
+                     static_cast<const V*>(a.x), static_cast<V*>(a.y), V(a.alpha), V(a.beta),
+                     a.read_y, a.cap, static_cast<const V*>(w), partial, done);
+  return hipGetLastError();
+}
+
+template <typename I, typename V, bool DA>
+hipError_t stream_dot(const SpmvArgs& a, int lanes, const void* w, double* partial,
+                      const int32_t* done) {
+  switch (lanes) {
+    case 1: return stream_dot_g<I, V, DA, 1>(a, w, partial, done);
+    case 2: return stream_dot_g<I, V, DA, 2>(a, w, partial, done);
+    case 4: return stream_dot_g<I, V, DA, 4>(a, w, partial, done);
+    case 8: return stream_dot_g<I, V, DA, 8>(a, w, partial, done);
+    default: return stream_dot_g<I, V, DA, 16>(a, w, partial, done);
+  }
+}
+
+// One index format with the value types of its translation unit.
+template <typename I, bool DA, typename S, typename V>
+hipError_t product(const SpmvArgs& a, int variant, int lanes, int unroll) {
+  return variant == DAMN_VAR_STREAM ? stream<I, S, V, DA>(a, lanes)
+                                    : vector<I, S, V, DA>(a, lanes, unroll);
+}
+
+}  // namespace launch
+}  // namespace damn

@@ -14,6 +14,7 @@ from .matrices import (  # noqa: F401
     laplace_2d_5pt,
     poisson_3d_7pt,
     stencil_3d_27pt,
+    stencil_3d_27pt_box,
     random_banded,
     scramble_symmetric,
     random_csr,

@@ -117,6 +117,14 @@ def stencil_3d_27pt(N: int, seed: int) -> CSR:
     Off-diagonal values uniform on [-1, 1]; the diagonal is 1 plus the sum of
     the absolute off-diagonal values of its row (strict diagonal dominance).
     """
+    A = stencil_3d_27pt_box(N, N, N, seed)
+    A.name = f"stencil3d_27pt_{N}^3"
+    return A
+
+
+def stencil_3d_27pt_box(nx: int, ny: int, nz: int, seed: int) -> CSR:
+    """The 27-point stencil of stencil_3d_27pt on an nx*ny*nz box (x
+    fastest); its bandwidth is 1 + nx + nx*ny."""
     offsets = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
 
     def values(valid, kd):
@@ -127,7 +135,7 @@ def stencil_3d_27pt(N: int, seed: int) -> CSR:
         v[:, kd] = 1.0 + np.abs(v).sum(axis=1)
         return v
 
-    return _grid_stencil((N, N, N), offsets, values, f"stencil3d_27pt_{N}^3")
+    return _grid_stencil((nx, ny, nz), offsets, values, f"stencil3d_27pt_{nx}x{ny}x{nz}")
 
 
 def random_banded(
@@ -137,20 +145,24 @@ def random_banded(
     mean_len: float = 12.0,
     sigma: float = 0.8,
     max_len: int = 200,
+    ncols: int | None = None,
 ) -> CSR:
-    """Random banded matrix.
+    """Random banded matrix, n x ncols (ncols = n by default).
 
     Row lengths are lognormal with the given mean and shape sigma, rounded
     and clipped to [1, max_len] (and to the row's window).  The columns of a
-    row are distinct, uniform over [max(0, r-half_band), min(n-1, r+half_band)],
-    sorted ascending; values are standard normal.
+    row are distinct, uniform over
+    [max(0, r-half_band), min(ncols-1, r+half_band)], sorted ascending (a row
+    whose window is empty, in a tall matrix, stays empty); values are
+    standard normal.
     """
+    m = n if ncols is None else ncols
     rng = np.random.default_rng(seed)
     mu = math.log(mean_len) - 0.5 * sigma * sigma
     rowlen = np.clip(np.rint(rng.lognormal(mu, sigma, n)), 1, max_len).astype(np.int64)
     r = np.arange(n, dtype=np.int64)
     lo = np.maximum(r - half_band, 0)
-    window = np.minimum(r + half_band, n - 1) - lo + 1
+    window = np.maximum(np.minimum(r + half_band, m - 1) - lo + 1, 0)
     rowlen = np.minimum(rowlen, window)
     del r
     rowptr = np.zeros(n + 1, dtype=np.int64)
@@ -158,9 +170,9 @@ def random_banded(
     nnz = int(rowptr[-1])
     rows = np.repeat(np.arange(n, dtype=np.int64), rowlen)
     cols = lo[rows] + rng.integers(0, window[rows], dtype=np.int64)
-    key = rows * n + cols
+    key = rows * m + cols
     key.sort()
-    cols = key - rows * n
+    cols = key - rows * m
     del key
     # redraw repeated columns until every row's columns are distinct
     while True:
@@ -175,7 +187,8 @@ def random_banded(
             cols[s:e].sort()
     del rows
     vals = rng.standard_normal(nnz)
-    return _finish(n, n, rowlen, cols.astype(np.int32), vals, f"banded_n{n}_hb{half_band}")
+    name = f"banded_n{n}_hb{half_band}" if m == n else f"banded_{n}x{m}_hb{half_band}"
+    return _finish(n, m, rowlen, cols.astype(np.int32), vals, name)
 
 
 def scramble_symmetric(A: CSR, seed: int) -> CSR:

@@ -422,6 +422,58 @@ def bench_grid(D, args):
     return out
 
 
+def bsr_model_bytes(nbrows, nbcols, nnzb, b, iindex, scalar=8):
+    # Eq. 3 with one index per block and b*b scalars per block, plus x and y
+    return 4 * (nbrows + 1) + nnzb * (iindex + b * b * scalar) + scalar * b * (nbcols + nbrows)
+
+
+def bench_blocks(D, args):
+    """DA-BSR against BSR (Sec. 1: diagonal addressing applied to block
+    storage) on a block matrix of the finite-element kind: 3 x 3 blocks on
+    the 27-point pattern of a 64^3 node grid (786,432 rows, 6.86M blocks),
+    float64 and float32; the same matrix in scalar DA-CSR and CSR."""
+    import torch
+
+    from paper_2307_06305_amd.tuning import autotune, config_name
+    from workloads.matrices import block_stencil_27pt, uniform_vector
+
+    b = 3
+    A = block_stencil_27pt(64, b, 1010)
+    x64 = uniform_vector(A.ncols, 2010)
+    nbr = A.nrows // b
+    out = {"workload": "block3_stencil27_64^3", "rows": A.nrows, "nnz": A.nnz, "block": b}
+    for fmt, name, ib in ((D.FORMAT_BSR32, "bsr32", 4), (D.FORMAT_DABSR16, "dabsr16", 2)):
+        e = D.bsr_encode(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, b, fmt)
+        nnzb = len(e["bidx"])
+        out["nnzb"] = nnzb
+        out["block_bandwidth"] = e["wb"]
+        for store, sname, sb in ((D.F64, "f64", 8), (D.F32, "f32", 4)):
+            M = D.Matrix.bsr_create(fmt, nbr, nbr, b, e["browptr"], e["bidx"], e["bvals"],
+                                    store=store)
+            tdt = torch.float64 if store == D.F64 else torch.float32
+            x = torch.from_numpy(x64).to("cuda", tdt)
+            y = torch.zeros(A.nrows, dtype=tdt, device="cuda")
+            best, _ = autotune(M, x, y, reps=args.tune_reps)
+            t = epochs(lambda: M.apply(x, y), 30)
+            T = bsr_model_bytes(nbr, nbr, nnzb, b, ib, sb)
+            out[f"{name}_{sname}"] = {"us": round(t * 1e6, 2), "model_bytes": T,
+                                      "gbs": round(T / t / 1e9, 1), "launch": config_name(best)}
+            log(f"blocks {name} {sname}: {out[f'{name}_{sname}']}")
+            M.destroy()
+        del e
+    for fmt, name in ((D.FORMAT_CSR32, "csr32"), (D.FORMAT_DA16, "da16")):
+        c = _grid_cell(D, A, fmt, D.F64, x64, args.tune_reps)
+        out[f"{name}_f64"] = c
+        log(f"blocks scalar {name}: {c}")
+    for s in ("f64", "f32"):
+        out[f"speedup_dabsr_over_bsr_{s}"] = round(
+            out[f"bsr32_{s}"]["us"] / out[f"dabsr16_{s}"]["us"], 4)
+        out[f"predicted_{s}"] = round(
+            out[f"bsr32_{s}"]["model_bytes"] / out[f"dabsr16_{s}"]["model_bytes"], 4)
+    out["speedup_dabsr_over_csr32_f64"] = round(out["csr32_f64"]["us"] / out["dabsr16_f64"]["us"], 4)
+    return out
+
+
 def bench_batch(D, args):
     """512 DA-CSR matrices (n log-uniform on [1e3, 2e5]; 2D 5-point, 3D
     7-point, 3D 27-point and random banded; 1-8 right-hand sides): one
@@ -544,6 +596,7 @@ def main():
     ap.add_argument("--skip-cube", action="store_true", help="skip the 256^3 CSR CG solves")
     ap.add_argument("--skip-grid", action="store_true",
                     help="skip the index / scalar width grid and the non-square products")
+    ap.add_argument("--skip-blocks", action="store_true", help="skip the DA-BSR / BSR products")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-workgroups", type=int, default=0)
     ap.add_argument("--profile", action="store_true",
@@ -701,6 +754,8 @@ def main():
         res["sweep"] = bench_sweep(D, args)
     if not args.skip_grid:
         res["grid"] = bench_grid(D, args)
+    if not args.skip_blocks:
+        res["blocks"] = bench_blocks(D, args)
     if not args.skip_batch:
         res["batch"] = bench_batch(D, args)
         res["selector_training"] = bench_selector_training(D, args)

@@ -67,7 +67,9 @@ typedef enum {
   DAMN_FORMAT_DA16 = 0,
   DAMN_FORMAT_CSR32 = 1,
   DAMN_FORMAT_DA8 = 2,
-  DAMN_FORMAT_CSR16 = 3
+  DAMN_FORMAT_CSR16 = 3,
+  DAMN_FORMAT_DABSR16 = 4, /* b x b blocks, int16 block offsets bc - br    */
+  DAMN_FORMAT_BSR32 = 5    /* b x b blocks, int32 block columns bc         */
 } damn_format;
 
 /* Opaque device matrix; owns its device arrays. */
@@ -156,6 +158,30 @@ int damn_encode(int32_t nrows, int32_t ncols, const int32_t* rowptr,
 int damn_encode_index(int32_t format, int32_t nrows, int32_t ncols, const int32_t* rowptr,
                       const int32_t* colids, void* idx_out, int32_t* w_out);
 
+/* Block storage (Sec. 1: diagonal addressing applies to BSR as well).  The
+ * matrix is cut into b x b blocks (nrows and ncols multiples of b); a block
+ * is stored when a pattern entry (stored zeros included) falls into it.  Per
+ * block row the stored blocks come in ascending block column, each with its
+ * b*b values row-major (zero where the pattern has no entry; repeated
+ * entries add up in storage order).  DA-BSR keeps the block offset bc - br
+ * in int16 and needs the block bandwidth max |bc - br| below 2^15; BSR keeps
+ * bc in int32.
+ *
+ * damn_bsr_count: *nnzb = stored blocks, *wb = block bandwidth (host).
+ * damn_bsr_encode: format DAMN_FORMAT_DABSR16 or DAMN_FORMAT_BSR32; writes
+ *   browptr_out[nrows/b + 1], bidx_out[nnzb] (int16 offsets or int32 block
+ *   columns) and bvals_out[nnzb*b*b] (float64), host, caller-allocated with
+ *   the sizes damn_bsr_count gives.
+ * Errors: DAMN_ERR_INVALID_ARG (b < 1, sizes not multiples of b, null
+ *         pointers), DAMN_ERR_BAD_CSR, DAMN_ERR_NO_FIT (DA-BSR with
+ *         wb >= 2^15), DAMN_ERR_UNSUPPORTED (2^31 blocks or more),
+ *         DAMN_ERR_ALLOC. */
+int damn_bsr_count(int32_t nrows, int32_t ncols, const int32_t* rowptr, const int32_t* colids,
+                   int32_t b, int64_t* nnzb, int32_t* wb);
+int damn_bsr_encode(int32_t nrows, int32_t ncols, const int32_t* rowptr, const int32_t* colids,
+                    const double* vals, int32_t b, int32_t format, int32_t* browptr_out,
+                    void* bidx_out, double* bvals_out);
+
 /* Values in a narrower scalar type (the scalar axis of Fig. 3): IEEE 754
  * round to nearest, ties to even, in one step from the input value (a
  * float64 value is never rounded to float32 on its way to float16).
@@ -210,10 +236,29 @@ int damn_create_format(damn_mat* out, int32_t format, int32_t nrows, int32_t nco
                        const int32_t* rowptr, const void* idx, const void* vals,
                        int32_t vals_dtype, int32_t store_dtype, void* stream);
 
+/* Upload a block matrix (DAMN_FORMAT_DABSR16 or DAMN_FORMAT_BSR32) with
+ * block size b in {2, 3, 4, 6}.
+ * In:  nbrows x nbcols blocks; host browptr[nbrows+1], bidx[nnzb] (int16
+ *      offsets or int32 block columns), bvals[nnzb*b*b] of vals_dtype,
+ *      stored as store_dtype (float64 or float32).  Every block column
+ *      (br + offset for DA-BSR) must lie in [0, nbcols); checked on the host.
+ * Out: *out; the handle is an (nbrows*b) x (nbcols*b) matrix: DA-BSR takes
+ *      damn_spmv and BSR damn_csr_spmv.  The products use the stream
+ *      variant with `lanes` lanes per scalar row (at most 16) and tiles of
+ *      about `tile` values.
+ * Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_BAD_CSR, DAMN_ERR_UNSUPPORTED (b,
+ *         float16), DAMN_ERR_NO_FIT (value overflow), DAMN_ERR_ALLOC,
+ *         DAMN_ERR_HIP. */
+int damn_bsr_create(damn_mat* out, int32_t format, int32_t nbrows, int32_t nbcols, int32_t b,
+                    const int32_t* browptr, const void* bidx, const void* bvals,
+                    int32_t vals_dtype, int32_t store_dtype, void* stream);
+
 /* Release a handle (waits for the device to finish using it). */
 int damn_destroy(damn_mat A);
 
-/* Shape and format of a handle (any out pointer may be NULL). */
+/* Shape and format of a handle (any out pointer may be NULL); nrows and
+ * ncols are scalar rows and columns, nnz counts stored entries (blocks for
+ * block formats). */
 int damn_mat_info(damn_mat A, int32_t* nrows, int32_t* ncols, int64_t* nnz,
                   int32_t* format, int32_t* dtype);
 
@@ -223,13 +268,15 @@ int damn_mat_info(damn_mat A, int32_t* nrows, int32_t* ncols, int64_t* nnz,
  * float16 handles (which accumulate in float32).
  * --------------------------------------------------------------------- */
 
-/* y <- alpha*A*x + beta*y for a DA handle (DA16 or DA8): row r accumulates
- * values[i] * x[r + off[i]] (the shifted-x access of Sec. 4).
- * Errors: DAMN_ERR_INVALID_ARG (null, or a CSR handle), DAMN_ERR_HIP. */
+/* y <- alpha*A*x + beta*y for a DA handle (DA16, DA8 or DA-BSR): row r
+ * accumulates values[i] * x[r + off[i]] (the shifted-x access of Sec. 4;
+ * for DA-BSR block row br reads x blocks br + offset).
+ * Errors: DAMN_ERR_INVALID_ARG (null, or a handle with absolute columns),
+ *         DAMN_ERR_HIP. */
 int damn_spmv(damn_mat A, const void* x, void* y, double alpha, double beta,
               void* stream);
 
-/* Same product for a CSR handle (CSR32 or CSR16, absolute columns). */
+/* Same product for handles with absolute columns (CSR32, CSR16, BSR32). */
 int damn_csr_spmv(damn_mat A, const void* x, void* y, double alpha,
                   double beta, void* stream);
 

@@ -20,11 +20,13 @@ from ._lib import DamnError, NoFit, lib, LIB_PATH  # noqa: F401
 
 F64, F32, F16 = 0, 1, 2
 FORMAT_DA16, FORMAT_CSR32, FORMAT_DA8, FORMAT_CSR16 = 0, 1, 2, 3
+FORMAT_DABSR16, FORMAT_BSR32 = 4, 5
 VAR_VECTOR, VAR_STREAM = 0, 1
 
 # the storage grid of Fig. 3: format -> (index dtype, holds DA offsets)
 FORMATS = {FORMAT_DA16: (np.int16, True), FORMAT_CSR32: (np.int32, False),
-           FORMAT_DA8: (np.int8, True), FORMAT_CSR16: (np.int16, False)}
+           FORMAT_DA8: (np.int8, True), FORMAT_CSR16: (np.int16, False),
+           FORMAT_DABSR16: (np.int16, True), FORMAT_BSR32: (np.int32, False)}
 VALUE_DTYPES = {F64: np.float64, F32: np.float32, F16: np.float16}
 
 _I32P = C.POINTER(C.c_int32)
@@ -145,6 +147,31 @@ def encode_index(fmt, nrows, ncols, rowptr, colids):
     return idx, w.value
 
 
+def bsr_encode(nrows, ncols, rowptr, colids, vals, b, fmt=FORMAT_DABSR16):
+    """int32 CSR -> BSR / DA-BSR with b x b blocks (host).  Returns
+    dict(browptr, bidx, bvals (nnzb, b, b), wb); raises NoFit (with .w = the
+    block bandwidth) for DA-BSR when it does not fit int16."""
+    c = _i32(colids)
+    v = np.ascontiguousarray(vals, dtype=np.float64)
+    rp = _csr_arrays(nrows, rowptr, c, v)
+    nnzb, wb = C.c_int64(), C.c_int32()
+    _check(lib.damn_bsr_count(nrows, ncols, _ptr(rp, C.c_int32), _ptr(c, C.c_int32), int(b),
+                              C.byref(nnzb), C.byref(wb)), "bsr_count")
+    if fmt not in (FORMAT_DABSR16, FORMAT_BSR32):
+        raise DamnError(-1, "bsr_encode: not a block format")
+    nb = nnzb.value
+    brp = np.empty(nrows // b + 1, dtype=np.int32)
+    bidx = np.empty(nb, dtype=FORMATS[fmt][0])
+    bvals = np.empty((nb, b, b), dtype=np.float64)
+    st = lib.damn_bsr_encode(nrows, ncols, _ptr(rp, C.c_int32), _ptr(c, C.c_int32),
+                             _ptr(v, C.c_double), int(b), int(fmt), _ptr(brp, C.c_int32),
+                             bidx.ctypes.data_as(C.c_void_p), _ptr(bvals, C.c_double))
+    if st == -3:
+        raise NoFit(wb.value, "block bandwidth")
+    _check(st, "bsr_encode")
+    return {"browptr": brp, "bidx": bidx, "bvals": bvals, "wb": wb.value}
+
+
 def store_values(vals, dtype):
     """Values rounded to dtype (F64/F32/F16) as the library stores them
     (host).  Raises NoFit on overflow."""
@@ -197,6 +224,7 @@ class Matrix:
         self._h = handle
         self.nrows, self.ncols, self.nnz = nrows, ncols, nnz
         self.format, self.dtype = fmt, dtype
+        self.block = 1
 
     # construction -----------------------------------------------------------
     @classmethod
@@ -231,6 +259,28 @@ class Matrix:
                                       ix.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p),
                                       vd, int(store), _stream_ptr(stream)), "create_format")
         return cls(h, nrows, ncols, int(rp[nrows]), fmt, store)
+
+    @classmethod
+    def bsr_create(cls, fmt, nbrows, nbcols, b, browptr, bidx, bvals, store=F64, stream=None):
+        """Upload BSR (FORMAT_BSR32) or DA-BSR (FORMAT_DABSR16) with b x b
+        blocks; bvals has nnzb*b*b values (float64 or float32)."""
+        if fmt not in (FORMAT_DABSR16, FORMAT_BSR32):
+            raise DamnError(-1, "bsr_create: not a block format")
+        ix = np.ascontiguousarray(bidx, dtype=FORMATS[fmt][0])
+        v = np.ascontiguousarray(bvals).reshape(-1)
+        vd = F32 if v.dtype == np.float32 else F64
+        v = v.astype(np.float64 if vd == F64 else np.float32, copy=False)
+        rp = _csr_arrays(nbrows, browptr, ix)
+        if v.size != ix.size * b * b:
+            raise DamnError(-2, "bvals must hold nnzb*b*b values")
+        h = C.c_void_p()
+        _check(lib.damn_bsr_create(C.byref(h), int(fmt), nbrows, nbcols, int(b),
+                                   _ptr(rp, C.c_int32), ix.ctypes.data_as(C.c_void_p),
+                                   v.ctypes.data_as(C.c_void_p), vd, int(store),
+                                   _stream_ptr(stream)), "bsr_create")
+        M = cls(h, nbrows * b, nbcols * b, int(rp[nbrows]), fmt, store)
+        M.block = b
+        return M
 
     @classmethod
     def csr_create(cls, nrows, ncols, rowptr, colids, vals, store=F64, stream=None):

@@ -22,9 +22,10 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdamn.so")
 
 ARCH = "gfx950"
-HIP_SOURCES = ["spmv_kernels.hip", "spmv_grid.hip", "api.hip", "cg.hip", "batch.hip",
-               "selector.hip"]
-CPP_SOURCES = ["host_format.cpp", "host_grid.cpp", "host_rcm.cpp", "host_features.cpp"]
+HIP_SOURCES = ["spmv_kernels.hip", "spmv_grid.hip", "spmv_bsr.hip", "api.hip", "cg.hip",
+               "batch.hip", "selector.hip"]
+CPP_SOURCES = ["host_format.cpp", "host_grid.cpp", "host_blocks.cpp", "host_rcm.cpp",
+               "host_features.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"]
 # packed fp32 vector instructions are disabled for device code

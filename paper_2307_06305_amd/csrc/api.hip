@@ -20,19 +20,21 @@ int build_tiles(damn_mat A, int32_t cap) {
   if (A->d_tiles && A->tiles_cap == cap) return DAMN_OK;
   std::vector<int32_t> starts;
   try {
-    starts.reserve(size_t(A->nrows / 8 + 2));
+    // rows of the stored structure: block rows for block formats
+    const int32_t nr = int32_t(A->h_rowptr.size()) - 1;
+    starts.reserve(size_t(nr / 8 + 2));
     const int32_t* rp = A->h_rowptr.data();
     int32_t r = 0;
-    while (r < A->nrows) {
+    while (r < nr) {
       starts.push_back(r);
       const int32_t first = r;
       if (rp[r + 1] - rp[r] > cap) {
         ++r;
         continue;
       }
-      while (r < A->nrows && r - first < kMaxTileRows && rp[r + 1] - rp[first] <= cap) ++r;
+      while (r < nr && r - first < kMaxTileRows && rp[r + 1] - rp[first] <= cap) ++r;
     }
-    starts.push_back(A->nrows);
+    starts.push_back(nr);
   } catch (const std::bad_alloc&) {
     return DAMN_ERR_ALLOC;
   }
@@ -84,6 +86,14 @@ damn_config default_config(int32_t nrows, int64_t nnz) {
 
 bool valid_pow2_lanes(int32_t l) { return l >= 1 && l <= 64 && (l & (l - 1)) == 0; }
 
+// Tile cap of the stream variant for a configured tile size: entries, or
+// for block formats blocks of about `tile` values (at least 8).
+int32_t tile_cap(damn_mat A, int32_t tile) {
+  if (A->block <= 1) return tile;
+  const int32_t c = tile / (A->block * A->block);
+  return c < 8 ? 8 : c;
+}
+
 void free_mat(damn_mat A) {
   if (!A) return;
   int cur = 0;
@@ -102,7 +112,7 @@ void free_mat(damn_mat A) {
 // from vals_dtype to store_dtype (damn_store_values).
 int create_common(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* rowptr,
                   const void* idx, const void* vals, int32_t vals_dtype, int32_t store_dtype,
-                  void* stream, int32_t format) {
+                  void* stream, int32_t format, int64_t vals_per_entry = 1) {
   if (out == nullptr || rowptr == nullptr) return DAMN_ERR_INVALID_ARG;
   if (value_bytes(vals_dtype) == 0 || value_bytes(store_dtype) == 0) return DAMN_ERR_INVALID_ARG;
   if (value_bytes(store_dtype) > value_bytes(vals_dtype)) return DAMN_ERR_UNSUPPORTED;
@@ -129,9 +139,11 @@ int create_common(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* ro
 
   const size_t vsize = size_t(value_bytes(store_dtype));
   const int64_t pe = padded_entries(nnz);
+  const int64_t nv = nnz * vals_per_entry;  // values: b*b per block for block formats
+  const int64_t pv = padded_entries(nv);
   if (hipMalloc(&A->d_rowptr, sizeof(int32_t) * (size_t(nrows) + 1 + kRowptrPad)) != hipSuccess ||
       hipMalloc(&A->d_idx, idx_size * pe) != hipSuccess ||
-      hipMalloc(&A->d_val, vsize * pe) != hipSuccess) {
+      hipMalloc(&A->d_val, vsize * pv) != hipSuccess) {
     free_mat(A);
     return DAMN_ERR_ALLOC;
   }
@@ -139,12 +151,12 @@ int create_common(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* ro
   const void* src_vals = vals;
   if (store_dtype != vals_dtype) {
     try {
-      conv.resize(size_t(nnz) * vsize);
+      conv.resize(size_t(nv) * vsize);
     } catch (const std::bad_alloc&) {
       free_mat(A);
       return DAMN_ERR_ALLOC;
     }
-    const int st = damn_store_values(nnz, vals, vals_dtype, store_dtype, conv.data());
+    const int st = damn_store_values(nv, vals, vals_dtype, store_dtype, conv.data());
     if (st != DAMN_OK) {
       free_mat(A);
       return st;
@@ -154,12 +166,12 @@ int create_common(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* ro
   bool ok = hipMemsetAsync(A->d_rowptr, 0, sizeof(int32_t) * (size_t(nrows) + 1 + kRowptrPad),
                            s) == hipSuccess &&
             hipMemsetAsync(A->d_idx, 0, idx_size * pe, s) == hipSuccess &&
-            hipMemsetAsync(A->d_val, 0, vsize * pe, s) == hipSuccess &&
+            hipMemsetAsync(A->d_val, 0, vsize * pv, s) == hipSuccess &&
             hipMemcpyAsync(A->d_rowptr, rowptr, sizeof(int32_t) * (size_t(nrows) + 1),
                            hipMemcpyHostToDevice, s) == hipSuccess;
   if (ok && nnz > 0)
     ok = hipMemcpyAsync(A->d_idx, idx, idx_size * nnz, hipMemcpyHostToDevice, s) == hipSuccess &&
-         hipMemcpyAsync(A->d_val, src_vals, vsize * nnz, hipMemcpyHostToDevice, s) ==
+         hipMemcpyAsync(A->d_val, src_vals, vsize * nv, hipMemcpyHostToDevice, s) ==
              hipSuccess;
   if (ok) ok = hipStreamSynchronize(s) == hipSuccess;
   if (!ok) {
@@ -189,6 +201,22 @@ int run_spmv(damn_mat A, const void* x, void* y, double alpha, double beta, void
   a.format = A->format;
   a.store = A->dtype;
   a.stream = static_cast<hipStream_t>(stream);
+  if (A->block > 1) {
+    // block formats: the stream variant only, at most 16 lanes per row
+    if (alpha == 0.0) {  // y <- beta*y: no tiles needed
+      const hipError_t e = launch_spmv(a, DAMN_VAR_VECTOR, 1, 1);
+      return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
+    }
+    const int32_t tile = A->cfg.variant == DAMN_VAR_STREAM ? A->cfg.tile : 2048;
+    const int st = build_tiles(A, tile_cap(A, tile));
+    if (st != DAMN_OK) return st;
+    a.block = A->block;
+    a.tile_row = A->d_tiles;
+    a.ntiles = A->ntiles;
+    a.cap = A->tiles_cap;
+    const hipError_t e = launch_spmv_bsr(a, A->cfg.lanes > 16 ? 16 : A->cfg.lanes);
+    return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
+  }
   if (A->cfg.variant == DAMN_VAR_STREAM) {
     const int st = build_tiles(A, A->cfg.tile);
     if (st != DAMN_OK) return st;
@@ -260,11 +288,59 @@ int damn_csr_create(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* 
                        DAMN_FORMAT_CSR32);
 }
 
+int damn_bsr_create(damn_mat* out, int32_t format, int32_t nbrows, int32_t nbcols, int32_t b,
+                    const int32_t* browptr, const void* bidx, const void* bvals,
+                    int32_t vals_dtype, int32_t store_dtype, void* stream) {
+  if (!format_is_block(format) || nbrows < 0 || nbcols < 0 || browptr == nullptr ||
+      out == nullptr)
+    return DAMN_ERR_INVALID_ARG;
+  if (b != 2 && b != 3 && b != 4 && b != 6) return DAMN_ERR_UNSUPPORTED;
+  if (store_dtype == DAMN_F16) return DAMN_ERR_UNSUPPORTED;
+  if (int64_t(nbrows) * b > INT32_MAX || int64_t(nbcols) * b > INT32_MAX)
+    return DAMN_ERR_UNSUPPORTED;
+  if (browptr[0] != 0) return DAMN_ERR_BAD_CSR;
+  for (int32_t r = 0; r < nbrows; ++r)
+    if (browptr[r + 1] < browptr[r]) return DAMN_ERR_BAD_CSR;
+  const int64_t nnzb = browptr[nbrows];
+  if (nnzb > 0 && (bidx == nullptr || bvals == nullptr)) return DAMN_ERR_INVALID_ARG;
+  if (nnzb * b * b >= (int64_t(1) << 31)) return DAMN_ERR_UNSUPPORTED;
+  const bool da = format == DAMN_FORMAT_DABSR16;
+  int32_t bad = 0;
+  parallel_for(nbrows, [&](int64_t lo, int64_t hi) {
+    int32_t local = 0;
+    for (int64_t r = lo; r < hi; ++r)
+      for (int64_t k = browptr[r]; k < browptr[r + 1]; ++k) {
+        const int64_t c = da ? r + static_cast<const int16_t*>(bidx)[k]
+                             : int64_t(static_cast<const int32_t*>(bidx)[k]);
+        local |= (c < 0) | (c >= nbcols);
+      }
+    if (local) __atomic_store_n(&bad, 1, __ATOMIC_RELAXED);
+  }, 4096);
+  if (bad) return DAMN_ERR_BAD_CSR;
+  // the values are nnzb*b*b scalars: upload as a matrix with that many
+  // entries, then describe the blocks
+  std::vector<int32_t> vrp;
+  try {
+    vrp.assign(browptr, browptr + nbrows + 1);
+  } catch (const std::bad_alloc&) {
+    return DAMN_ERR_ALLOC;
+  }
+  int st = create_common(out, nbrows, nbcols, vrp.data(), bidx, bvals, vals_dtype, store_dtype,
+                         stream, format, int64_t(b) * b);
+  if (st != DAMN_OK) return st;
+  damn_mat A = *out;
+  A->block = b;
+  A->nrows = nbrows * b;
+  A->ncols = nbcols * b;
+  return DAMN_OK;
+}
+
 int damn_create_format(damn_mat* out, int32_t format, int32_t nrows, int32_t ncols,
                        const int32_t* rowptr, const void* idx, const void* vals,
                        int32_t vals_dtype, int32_t store_dtype, void* stream) {
   const int ib = index_bytes(format);
-  if (ib == 0 || nrows < 0 || ncols < 0 || rowptr == nullptr) return DAMN_ERR_INVALID_ARG;
+  if (ib == 0 || format_is_block(format) || nrows < 0 || ncols < 0 || rowptr == nullptr)
+    return DAMN_ERR_INVALID_ARG;
   if (rowptr[0] != 0) return DAMN_ERR_BAD_CSR;
   for (int32_t r = 0; r < nrows; ++r)
     if (rowptr[r + 1] < rowptr[r]) return DAMN_ERR_BAD_CSR;
@@ -356,10 +432,14 @@ int damn_set_config(damn_mat A, const damn_config* cfg) {
   if (c.variant == DAMN_VAR_VECTOR) {
     if (c.unroll != 1 && c.unroll != 2 && c.unroll != 4) return DAMN_ERR_INVALID_ARG;
     if (c.tile == 0) c.tile = A->cfg.tile;
+    if (A->block > 1) {  // block formats run the stream variant with 2048-value tiles
+      const int st = build_tiles(A, tile_cap(A, 2048));
+      if (st != DAMN_OK) return st;
+    }
   } else {
     if (c.tile < 256 || c.tile > 4096 || (c.tile % 8) != 0) return DAMN_ERR_UNSUPPORTED;
     if (c.unroll == 0) c.unroll = 1;
-    const int st = build_tiles(A, c.tile);
+    const int st = build_tiles(A, tile_cap(A, c.tile));
     if (st != DAMN_OK) return st;
   }
   A->cfg = c;

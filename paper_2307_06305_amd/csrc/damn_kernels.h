@@ -29,6 +29,7 @@ struct SpmvArgs {
   int32_t read_y = 0;  // beta != 0
   int32_t format = DAMN_FORMAT_DA16;
   int32_t store = DAMN_F64;  // x, y and sums are float64 for DAMN_F64, else float32
+  int32_t block = 1;         // block formats: b (rowptr and tiles count block rows)
   // stream variant
   const int32_t* tile_row = nullptr;
   int64_t ntiles = 0;
@@ -40,6 +41,9 @@ struct SpmvArgs {
 hipError_t launch_spmv(const SpmvArgs& a, int variant, int lanes, int unroll);
 // The same for 8-bit DA, 16-bit CSR and float16 values (spmv_grid.hip).
 hipError_t launch_spmv_grid(const SpmvArgs& a, int variant, int lanes, int unroll);
+// Block formats (spmv_bsr.hip): the stream variant over tiles of block rows
+// with `cap` blocks; lanes in {1, 2, 4, 8, 16}; block in {2, 3, 4, 6}.
+hipError_t launch_spmv_bsr(const SpmvArgs& a, int lanes);
 // Stream variant with the conjugate-gradient epilogue: partial[t] = sum of
 // y_r * w_r over tile t (w = nullptr: w = y), skipped entirely when *done.
 // lanes in {1, 2, 4, 8, 16}; alpha != 0; DA16 or CSR32, float64 or float32.

@@ -16,12 +16,19 @@ int index_bytes(int32_t format) {
     case DAMN_FORMAT_CSR32: return 4;
     case DAMN_FORMAT_DA8: return 1;
     case DAMN_FORMAT_CSR16: return 2;
+    case DAMN_FORMAT_DABSR16: return 2;
+    case DAMN_FORMAT_BSR32: return 4;
     default: return 0;
   }
 }
 
 bool format_is_da(int32_t format) {
-  return format == DAMN_FORMAT_DA16 || format == DAMN_FORMAT_DA8;
+  return format == DAMN_FORMAT_DA16 || format == DAMN_FORMAT_DA8 ||
+         format == DAMN_FORMAT_DABSR16;
+}
+
+bool format_is_block(int32_t format) {
+  return format == DAMN_FORMAT_DABSR16 || format == DAMN_FORMAT_BSR32;
 }
 
 int value_bytes(int32_t dtype) {
@@ -86,7 +93,7 @@ extern "C" {
 int damn_encode_index(int32_t format, int32_t nrows, int32_t ncols, const int32_t* rowptr,
                       const int32_t* colids, void* idx_out, int32_t* w_out) {
   const int ib = index_bytes(format);
-  if (ib == 0 || w_out == nullptr) return DAMN_ERR_INVALID_ARG;
+  if (ib == 0 || format_is_block(format) || w_out == nullptr) return DAMN_ERR_INVALID_ARG;
   const int st = check_csr(nrows, ncols, rowptr, colids);
   if (st != DAMN_OK) return st;
   const int64_t nnz = rowptr[nrows];

@@ -28,8 +28,8 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/spmv_kernels.hip", "csrc/spmv_templates.h", "csrc/damn_device.h")
-DA_KERNEL = "spmv_stream<short, double, true, 2, false>"
-CSR_KERNEL = "spmv_stream<int, double, false, 2, false>"
+DA_KERNEL = "spmv_stream<short, double, true, 2, false, double>"
+CSR_KERNEL = "spmv_stream<int, double, false, 2, false, double>"
 COPY_KERNEL = "stream_copy"
 
 

@@ -138,6 +138,46 @@ def stencil_3d_27pt_box(nx: int, ny: int, nz: int, seed: int) -> CSR:
     return _grid_stencil((nx, ny, nz), offsets, values, f"stencil3d_27pt_{nx}x{ny}x{nz}")
 
 
+def block_stencil_27pt(N: int, b: int, seed: int) -> CSR:
+    """A block matrix of the kind finite elements give with b unknowns per
+    node: the 27-point stencil pattern on an N^3 grid of nodes, each node
+    pair coupled by a dense b x b block (so every block is stored).
+
+    Values uniform on [-1, 1]; each diagonal entry is 1 plus the sum of the
+    absolute values of its row.  Scalar rows come in node order, the b
+    unknowns of a node adjacent; within a row, entries by block then column.
+    """
+    P = stencil_3d_27pt(N, seed)
+    nbr, nnzb = P.nrows, P.nnz
+    rp = P.rowptr.astype(np.int64)
+    bc = P.colids.astype(np.int64)
+    rl = np.diff(rp)
+    br = np.repeat(np.arange(nbr, dtype=np.int64), rl)
+    kk = np.arange(nnzb, dtype=np.int64) - rp[br]        # block position in its block row
+    i = np.arange(b, dtype=np.int64)[None, :, None]
+    j = np.arange(b, dtype=np.int64)[None, None, :]
+    # position of entry (k, i, j): row br*b + i starts at rp[br]*b*b + i*rl[br]*b
+    pos = (rp[br] * b * b)[:, None, None] + i * (rl[br] * b)[:, None, None] + kk[:, None, None] * b + j
+    rows = (br * b)[:, None, None] + i + 0 * j
+    cols = (bc * b)[:, None, None] + j + 0 * i
+    rng = np.random.default_rng(seed + 7919 * b)
+    vals_kij = rng.uniform(-1.0, 1.0, size=(nnzb, b, b))
+    nnz = nnzb * b * b
+    colids = np.empty(nnz, dtype=np.int64)
+    vals = np.empty(nnz)
+    rowof = np.empty(nnz, dtype=np.int64)
+    colids[pos.ravel()] = cols.ravel()
+    vals[pos.ravel()] = vals_kij.ravel()
+    rowof[pos.ravel()] = rows.ravel()
+    diag = rowof == colids
+    vals[diag] = 0.0
+    rowsum = np.bincount(rowof, weights=np.abs(vals), minlength=nbr * b)
+    vals[diag] = 1.0 + rowsum[rowof[diag]]
+    rowlen = np.repeat(rl * b, b)
+    return _finish(nbr * b, nbr * b, rowlen, colids.astype(np.int32), vals,
+                   f"block{b}_stencil27_{N}^3")
+
+
 def random_banded(
     n: int,
     seed: int,

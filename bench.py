@@ -474,6 +474,33 @@ def bench_blocks(D, args):
     return out
 
 
+def bench_coo(D, args):
+    """DA-COO against COO (Sec. 1: diagonal addressing applied to one index
+    vector of COO) on the 27-point 128^3 matrix; both stream a 4-byte row
+    index per entry on top of DA-CSR / CSR."""
+    import torch
+
+    from workloads import config_matrix, config_vector
+
+    A = config_matrix(1)
+    x = torch.from_numpy(config_vector(1, A.ncols)).to("cuda")
+    y = torch.zeros(A.nrows, dtype=torch.float64, device="cuda")
+    out = {"workload": "stencil3d_27pt_128^3", "n": A.nrows, "nnz": A.nnz}
+    for fmt, name, ib in ((D.FORMAT_COO32, "coo32", 4), (D.FORMAT_DACOO16, "dacoo16", 2)):
+        rows, idx = D.coo_encode(A.nrows, A.ncols, A.rowptr, A.colids, fmt)
+        M = D.Matrix.coo_create(fmt, A.nrows, A.ncols, rows, idx, A.vals)
+        del rows, idx
+        M.apply(x, y)
+        t = epochs(lambda: M.apply(x, y), 30)
+        T = A.nnz * (4 + ib + 8) + 8 * A.ncols + 8 * A.nrows
+        out[name] = {"us": round(t * 1e6, 2), "model_bytes": T, "gbs": round(T / t / 1e9, 1)}
+        log(f"coo {name}: {out[name]}")
+        M.destroy()
+    out["speedup"] = round(out["coo32"]["us"] / out["dacoo16"]["us"], 4)
+    out["predicted_speedup"] = round(out["coo32"]["model_bytes"] / out["dacoo16"]["model_bytes"], 4)
+    return out
+
+
 def bench_batch(D, args):
     """512 DA-CSR matrices (n log-uniform on [1e3, 2e5]; 2D 5-point, 3D
     7-point, 3D 27-point and random banded; 1-8 right-hand sides): one
@@ -597,6 +624,7 @@ def main():
     ap.add_argument("--skip-grid", action="store_true",
                     help="skip the index / scalar width grid and the non-square products")
     ap.add_argument("--skip-blocks", action="store_true", help="skip the DA-BSR / BSR products")
+    ap.add_argument("--skip-coo", action="store_true", help="skip the DA-COO / COO products")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-workgroups", type=int, default=0)
     ap.add_argument("--profile", action="store_true",
@@ -756,6 +784,8 @@ def main():
         res["grid"] = bench_grid(D, args)
     if not args.skip_blocks:
         res["blocks"] = bench_blocks(D, args)
+    if not args.skip_coo:
+        res["coo"] = bench_coo(D, args)
     if not args.skip_batch:
         res["batch"] = bench_batch(D, args)
         res["selector_training"] = bench_selector_training(D, args)

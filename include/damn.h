@@ -69,7 +69,9 @@ typedef enum {
   DAMN_FORMAT_DA8 = 2,
   DAMN_FORMAT_CSR16 = 3,
   DAMN_FORMAT_DABSR16 = 4, /* b x b blocks, int16 block offsets bc - br    */
-  DAMN_FORMAT_BSR32 = 5    /* b x b blocks, int32 block columns bc         */
+  DAMN_FORMAT_BSR32 = 5,   /* b x b blocks, int32 block columns bc         */
+  DAMN_FORMAT_DACOO16 = 6, /* coordinates: int32 row, int16 offset c - r   */
+  DAMN_FORMAT_COO32 = 7    /* coordinates: int32 row, int32 column         */
 } damn_format;
 
 /* Opaque device matrix; owns its device arrays. */
@@ -182,6 +184,19 @@ int damn_bsr_encode(int32_t nrows, int32_t ncols, const int32_t* rowptr, const i
                     const double* vals, int32_t b, int32_t format, int32_t* browptr_out,
                     void* bidx_out, double* bvals_out);
 
+/* Coordinate storage (Sec. 1: diagonal addressing applies to one of COO's
+ * index vectors).  Every entry keeps its int32 row; DA-COO stores the
+ * column as the int16 offset c - r (bandwidth below 2^15), COO as the int32
+ * column.  Entries are in row order (as CSR gives them; any order within a
+ * row).
+ * damn_coo_encode: from int32 CSR, entry order unchanged; rows_out[nnz],
+ *   idx_out[nnz] (int16 or int32), host, caller-allocated; *w_out = the
+ *   bandwidth (DA-COO) or the largest column (COO).
+ * Errors: DAMN_ERR_NO_FIT (DA-COO with w >= 2^15; only *w_out written),
+ *         DAMN_ERR_INVALID_ARG, DAMN_ERR_BAD_CSR. */
+int damn_coo_encode(int32_t format, int32_t nrows, int32_t ncols, const int32_t* rowptr,
+                    const int32_t* colids, int32_t* rows_out, void* idx_out, int32_t* w_out);
+
 /* Values in a narrower scalar type (the scalar axis of Fig. 3): IEEE 754
  * round to nearest, ties to even, in one step from the input value (a
  * float64 value is never rounded to float32 on its way to float16).
@@ -253,6 +268,22 @@ int damn_bsr_create(damn_mat* out, int32_t format, int32_t nbrows, int32_t nbcol
                     const int32_t* browptr, const void* bidx, const void* bvals,
                     int32_t vals_dtype, int32_t store_dtype, void* stream);
 
+/* Upload a coordinate matrix (DAMN_FORMAT_DACOO16 or DAMN_FORMAT_COO32).
+ * In:  nrows x ncols, nnz entries (below 2^31): host rows[nnz] (int32,
+ *      non-decreasing, in [0, nrows)), idx[nnz] (int16 offsets or int32
+ *      columns; every column inside [0, ncols)), vals[nnz] of vals_dtype
+ *      stored as store_dtype (float64 or float32).  All checked on the host.
+ * Out: *out.  DA-COO takes damn_spmv, COO damn_csr_spmv; a product writes
+ *      y <- beta*y first and then adds the rows' sums, each row in one
+ *      place, without atomics (the result does not depend on scheduling).
+ * Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_BAD_CSR (rows out of order or
+ *         range, columns out of range), DAMN_ERR_UNSUPPORTED (float16,
+ *         nnz >= 2^31), DAMN_ERR_NO_FIT (value overflow), DAMN_ERR_ALLOC,
+ *         DAMN_ERR_HIP. */
+int damn_coo_create(damn_mat* out, int32_t format, int32_t nrows, int32_t ncols, int64_t nnz,
+                    const int32_t* rows, const void* idx, const void* vals, int32_t vals_dtype,
+                    int32_t store_dtype, void* stream);
+
 /* Release a handle (waits for the device to finish using it). */
 int damn_destroy(damn_mat A);
 
@@ -268,7 +299,7 @@ int damn_mat_info(damn_mat A, int32_t* nrows, int32_t* ncols, int64_t* nnz,
  * float16 handles (which accumulate in float32).
  * --------------------------------------------------------------------- */
 
-/* y <- alpha*A*x + beta*y for a DA handle (DA16, DA8 or DA-BSR): row r
+/* y <- alpha*A*x + beta*y for a DA handle (DA16, DA8, DA-BSR, DA-COO): row r
  * accumulates values[i] * x[r + off[i]] (the shifted-x access of Sec. 4;
  * for DA-BSR block row br reads x blocks br + offset).
  * Errors: DAMN_ERR_INVALID_ARG (null, or a handle with absolute columns),
@@ -276,7 +307,8 @@ int damn_mat_info(damn_mat A, int32_t* nrows, int32_t* ncols, int64_t* nnz,
 int damn_spmv(damn_mat A, const void* x, void* y, double alpha, double beta,
               void* stream);
 
-/* Same product for handles with absolute columns (CSR32, CSR16, BSR32). */
+/* Same product for handles with absolute columns (CSR32, CSR16, BSR32,
+ * COO32). */
 int damn_csr_spmv(damn_mat A, const void* x, void* y, double alpha,
                   double beta, void* stream);
 

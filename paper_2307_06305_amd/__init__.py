@@ -21,12 +21,14 @@ from ._lib import DamnError, NoFit, lib, LIB_PATH  # noqa: F401
 F64, F32, F16 = 0, 1, 2
 FORMAT_DA16, FORMAT_CSR32, FORMAT_DA8, FORMAT_CSR16 = 0, 1, 2, 3
 FORMAT_DABSR16, FORMAT_BSR32 = 4, 5
+FORMAT_DACOO16, FORMAT_COO32 = 6, 7
 VAR_VECTOR, VAR_STREAM = 0, 1
 
 # the storage grid of Fig. 3: format -> (index dtype, holds DA offsets)
 FORMATS = {FORMAT_DA16: (np.int16, True), FORMAT_CSR32: (np.int32, False),
            FORMAT_DA8: (np.int8, True), FORMAT_CSR16: (np.int16, False),
-           FORMAT_DABSR16: (np.int16, True), FORMAT_BSR32: (np.int32, False)}
+           FORMAT_DABSR16: (np.int16, True), FORMAT_BSR32: (np.int32, False),
+           FORMAT_DACOO16: (np.int16, True), FORMAT_COO32: (np.int32, False)}
 VALUE_DTYPES = {F64: np.float64, F32: np.float32, F16: np.float16}
 
 _I32P = C.POINTER(C.c_int32)
@@ -172,6 +174,26 @@ def bsr_encode(nrows, ncols, rowptr, colids, vals, b, fmt=FORMAT_DABSR16):
     return {"browptr": brp, "bidx": bidx, "bvals": bvals, "wb": wb.value}
 
 
+def coo_encode(nrows, ncols, rowptr, colids, fmt=FORMAT_DACOO16):
+    """int32 CSR -> coordinates, entry order unchanged (host).  Returns
+    (rows int32, idx) with idx the int16 offsets (DA-COO) or int32 columns;
+    raises NoFit for DA-COO when the bandwidth does not fit int16."""
+    c = _i32(colids)
+    rp = _csr_arrays(nrows, rowptr, c)
+    if fmt not in (FORMAT_DACOO16, FORMAT_COO32):
+        raise DamnError(-1, "coo_encode: not a coordinate format")
+    nnz = int(rp[nrows])
+    rows = np.empty(nnz, dtype=np.int32)
+    idx = np.empty(nnz, dtype=FORMATS[fmt][0])
+    w = C.c_int32()
+    st = lib.damn_coo_encode(int(fmt), nrows, ncols, _ptr(rp, C.c_int32), _ptr(c, C.c_int32),
+                             _ptr(rows, C.c_int32), idx.ctypes.data_as(C.c_void_p), C.byref(w))
+    if st == -3:
+        raise NoFit(w.value)
+    _check(st, "coo_encode")
+    return rows, idx
+
+
 def store_values(vals, dtype):
     """Values rounded to dtype (F64/F32/F16) as the library stores them
     (host).  Raises NoFit on overflow."""
@@ -281,6 +303,26 @@ class Matrix:
         M = cls(h, nbrows * b, nbcols * b, int(rp[nbrows]), fmt, store)
         M.block = b
         return M
+
+    @classmethod
+    def coo_create(cls, fmt, nrows, ncols, rows, idx, vals, store=F64, stream=None):
+        """Upload coordinates (FORMAT_DACOO16 or FORMAT_COO32), entries in row
+        order; vals float64 or float32."""
+        if fmt not in (FORMAT_DACOO16, FORMAT_COO32):
+            raise DamnError(-1, "coo_create: not a coordinate format")
+        r = _i32(rows)
+        ix = np.ascontiguousarray(idx, dtype=FORMATS[fmt][0])
+        v = np.ascontiguousarray(vals)
+        vd = F32 if v.dtype == np.float32 else F64
+        v = v.astype(np.float64 if vd == F64 else np.float32, copy=False)
+        if not (r.size == ix.size == v.size):
+            raise DamnError(-2, "rows, idx and vals must have the same length")
+        h = C.c_void_p()
+        _check(lib.damn_coo_create(C.byref(h), int(fmt), nrows, ncols, r.size,
+                                   _ptr(r, C.c_int32), ix.ctypes.data_as(C.c_void_p),
+                                   v.ctypes.data_as(C.c_void_p), vd, int(store),
+                                   _stream_ptr(stream)), "coo_create")
+        return cls(h, nrows, ncols, int(r.size), fmt, store)
 
     @classmethod
     def csr_create(cls, nrows, ncols, rowptr, colids, vals, store=F64, stream=None):

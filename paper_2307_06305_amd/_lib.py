@@ -69,6 +69,9 @@ _SIGS = {
                                   _pf64]),
     "damn_bsr_create": (C.c_int, [C.POINTER(_vp), _i32, _i32, _i32, _i32, _pi32, _vp, _vp, _i32,
                                   _i32, _vp]),
+    "damn_coo_encode": (C.c_int, [_i32, _i32, _i32, _pi32, _pi32, _pi32, _vp, _pi32]),
+    "damn_coo_create": (C.c_int, [C.POINTER(_vp), _i32, _i32, _i32, _i64, _pi32, _vp, _vp, _i32,
+                                  _i32, _vp]),
     "damn_destroy": (C.c_int, [_vp]),
     "damn_mat_info": (C.c_int, [_vp, _pi32, _pi32, _pi64, _pi32, _pi32]),
     "damn_spmv": (C.c_int, [_vp, _vp, _vp, _f64, _f64, _vp]),

@@ -103,6 +103,8 @@ void free_mat(damn_mat A) {
   if (A->d_idx) hipFree(A->d_idx);
   if (A->d_val) hipFree(A->d_val);
   if (A->d_tiles) hipFree(A->d_tiles);
+  if (A->d_rows) hipFree(A->d_rows);
+  if (A->d_carry) hipFree(A->d_carry);
   release_cg_work(A);
   hipSetDevice(cur);
   delete A;
@@ -201,6 +203,14 @@ int run_spmv(damn_mat A, const void* x, void* y, double alpha, double beta, void
   a.format = A->format;
   a.store = A->dtype;
   a.stream = static_cast<hipStream_t>(stream);
+  if (format_is_coo(A->format)) {
+    a.nnz = A->nnz;
+    a.coo_rows = A->d_rows;
+    a.coo_carry = static_cast<CooCarry*>(A->d_carry);
+    a.nchunks = A->nchunks;
+    const hipError_t e = launch_spmv_coo(a);
+    return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
+  }
   if (A->block > 1) {
     // block formats: the stream variant only, at most 16 lanes per row
     if (alpha == 0.0) {  // y <- beta*y: no tiles needed
@@ -325,13 +335,65 @@ int damn_bsr_create(damn_mat* out, int32_t format, int32_t nbrows, int32_t nbcol
   } catch (const std::bad_alloc&) {
     return DAMN_ERR_ALLOC;
   }
-  int st = create_common(out, nbrows, nbcols, vrp.data(), bidx, bvals, vals_dtype, store_dtype,
+  damn_mat A = nullptr;
+  int st = create_common(&A, nbrows, nbcols, vrp.data(), bidx, bvals, vals_dtype, store_dtype,
                          stream, format, int64_t(b) * b);
   if (st != DAMN_OK) return st;
-  damn_mat A = *out;
   A->block = b;
   A->nrows = nbrows * b;
   A->ncols = nbcols * b;
+  *out = A;
+  return DAMN_OK;
+}
+
+int damn_coo_create(damn_mat* out, int32_t format, int32_t nrows, int32_t ncols, int64_t nnz,
+                    const int32_t* rows, const void* idx, const void* vals, int32_t vals_dtype,
+                    int32_t store_dtype, void* stream) {
+  if (!format_is_coo(format) || out == nullptr || nrows < 0 || ncols < 0 || nnz < 0)
+    return DAMN_ERR_INVALID_ARG;
+  if (store_dtype == DAMN_F16 || nnz >= (int64_t(1) << 31)) return DAMN_ERR_UNSUPPORTED;
+  if (nnz > 0 && (rows == nullptr || idx == nullptr || vals == nullptr))
+    return DAMN_ERR_INVALID_ARG;
+  // rows in order and range, columns in range; the row pointers follow
+  std::vector<int32_t> rp;
+  try {
+    rp.assign(size_t(nrows) + 1, 0);
+  } catch (const std::bad_alloc&) {
+    return DAMN_ERR_ALLOC;
+  }
+  const bool da = format == DAMN_FORMAT_DACOO16;
+  for (int64_t i = 0; i < nnz; ++i) {
+    const int32_t r = rows[i];
+    if (r < 0 || r >= nrows || (i > 0 && r < rows[i - 1])) return DAMN_ERR_BAD_CSR;
+    const int64_t c = da ? int64_t(r) + static_cast<const int16_t*>(idx)[i]
+                         : int64_t(static_cast<const int32_t*>(idx)[i]);
+    if (c < 0 || c >= ncols) return DAMN_ERR_BAD_CSR;
+    ++rp[size_t(r) + 1];
+  }
+  for (int32_t r = 0; r < nrows; ++r) rp[r + 1] += rp[r];
+  damn_mat A = nullptr;
+  int st = create_common(&A, nrows, ncols, rp.data(), idx, vals, vals_dtype, store_dtype, stream,
+                         format);
+  if (st != DAMN_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  A->nchunks = (nnz + kCooChunk - 1) / kCooChunk;
+  const int64_t pe = padded_entries(nnz);
+  bool ok = hipMalloc(&A->d_rows, sizeof(int32_t) * pe) == hipSuccess &&
+            hipMalloc(&A->d_carry, sizeof(CooCarry) * size_t(A->nchunks > 0 ? A->nchunks : 1)) ==
+                hipSuccess;
+  if (!ok) {
+    free_mat(A);
+    return DAMN_ERR_ALLOC;
+  }
+  ok = hipMemsetAsync(A->d_rows, 0, sizeof(int32_t) * pe, s) == hipSuccess &&
+       (nnz == 0 || hipMemcpyAsync(A->d_rows, rows, sizeof(int32_t) * nnz,
+                                   hipMemcpyHostToDevice, s) == hipSuccess) &&
+       hipStreamSynchronize(s) == hipSuccess;
+  if (!ok) {
+    free_mat(A);
+    return DAMN_ERR_HIP;
+  }
+  *out = A;
   return DAMN_OK;
 }
 
@@ -339,7 +401,8 @@ int damn_create_format(damn_mat* out, int32_t format, int32_t nrows, int32_t nco
                        const int32_t* rowptr, const void* idx, const void* vals,
                        int32_t vals_dtype, int32_t store_dtype, void* stream) {
   const int ib = index_bytes(format);
-  if (ib == 0 || format_is_block(format) || nrows < 0 || ncols < 0 || rowptr == nullptr)
+  if (ib == 0 || format_is_block(format) || format_is_coo(format) || nrows < 0 || ncols < 0 ||
+      rowptr == nullptr)
     return DAMN_ERR_INVALID_ARG;
   if (rowptr[0] != 0) return DAMN_ERR_BAD_CSR;
   for (int32_t r = 0; r < nrows; ++r)

@@ -50,6 +50,7 @@ constexpr int32_t kRefineSweeps = 32;
 int index_bytes(int32_t format);
 bool format_is_da(int32_t format);
 bool format_is_block(int32_t format);
+bool format_is_coo(int32_t format);
 int value_bytes(int32_t dtype);
 
 }  // namespace damn

@@ -15,6 +15,9 @@ struct damn_mat_s {
   int32_t format = DAMN_FORMAT_DA16;
   int32_t dtype = DAMN_F64;
   int32_t block = 1;  // b of block formats (rowptr, idx and tiles count block rows)
+  int32_t* d_rows = nullptr;  // coordinate formats: row of each entry, padded
+  void* d_carry = nullptr;    // coordinate formats: one CooCarry per chunk
+  int64_t nchunks = 0;
   int32_t* d_rowptr = nullptr;
   void* d_idx = nullptr;  // int16 offsets or int32 columns, padded
   void* d_val = nullptr;  // float64 or float32 values, padded

@@ -18,13 +18,19 @@ int index_bytes(int32_t format) {
     case DAMN_FORMAT_CSR16: return 2;
     case DAMN_FORMAT_DABSR16: return 2;
     case DAMN_FORMAT_BSR32: return 4;
+    case DAMN_FORMAT_DACOO16: return 2;
+    case DAMN_FORMAT_COO32: return 4;
     default: return 0;
   }
 }
 
 bool format_is_da(int32_t format) {
   return format == DAMN_FORMAT_DA16 || format == DAMN_FORMAT_DA8 ||
-         format == DAMN_FORMAT_DABSR16;
+         format == DAMN_FORMAT_DABSR16 || format == DAMN_FORMAT_DACOO16;
+}
+
+bool format_is_coo(int32_t format) {
+  return format == DAMN_FORMAT_DACOO16 || format == DAMN_FORMAT_COO32;
 }
 
 bool format_is_block(int32_t format) {
@@ -93,7 +99,8 @@ extern "C" {
 int damn_encode_index(int32_t format, int32_t nrows, int32_t ncols, const int32_t* rowptr,
                       const int32_t* colids, void* idx_out, int32_t* w_out) {
   const int ib = index_bytes(format);
-  if (ib == 0 || format_is_block(format) || w_out == nullptr) return DAMN_ERR_INVALID_ARG;
+  if (ib == 0 || format_is_block(format) || format_is_coo(format) || w_out == nullptr)
+    return DAMN_ERR_INVALID_ARG;
   const int st = check_csr(nrows, ncols, rowptr, colids);
   if (st != DAMN_OK) return st;
   const int64_t nnz = rowptr[nrows];
@@ -120,6 +127,38 @@ int damn_encode_index(int32_t format, int32_t nrows, int32_t ncols, const int32_
           static_cast<int16_t*>(idx_out)[i] = int16_t(v);
         else
           static_cast<int32_t*>(idx_out)[i] = int32_t(v);
+      }
+  }, 4096);
+  return DAMN_OK;
+}
+
+int damn_coo_encode(int32_t format, int32_t nrows, int32_t ncols, const int32_t* rowptr,
+                    const int32_t* colids, int32_t* rows_out, void* idx_out, int32_t* w_out) {
+  if (!format_is_coo(format) || w_out == nullptr) return DAMN_ERR_INVALID_ARG;
+  const int st = check_csr(nrows, ncols, rowptr, colids);
+  if (st != DAMN_OK) return st;
+  const int64_t nnz = rowptr[nrows];
+  if (nnz > 0 && (rows_out == nullptr || idx_out == nullptr)) return DAMN_ERR_INVALID_ARG;
+  const bool da = format == DAMN_FORMAT_DACOO16;
+  int64_t w = 0;
+  if (da) {
+    int64_t lo = 0, hi = 0;
+    bandwidth(nrows, rowptr, colids, &lo, &hi);
+    w = std::max(lo, hi);
+    *w_out = int32_t(w);
+    if (w >= kInt16BandwidthLimit) return DAMN_ERR_NO_FIT;
+  } else {
+    for (int64_t i = 0; i < nnz; ++i) w = std::max<int64_t>(w, colids[i]);
+    *w_out = int32_t(w);
+  }
+  parallel_for(nrows, [&](int64_t b, int64_t e) {
+    for (int64_t r = b; r < e; ++r)
+      for (int64_t i = rowptr[r]; i < rowptr[r + 1]; ++i) {
+        rows_out[i] = int32_t(r);
+        if (da)
+          static_cast<int16_t*>(idx_out)[i] = int16_t(colids[i] - r);
+        else
+          static_cast<int32_t*>(idx_out)[i] = colids[i];
       }
   }, 4096);
   return DAMN_OK;

@@ -572,11 +572,16 @@ def bench_batch(D, args):
     info = B.info()
     t_graph = epochs(lambda: B.run(use_graph=True), 10, 5)
     t_direct = epochs(lambda: B.run(use_graph=False), 10, 5)
+    # the persistent grid (1024 workgroups walking equal-work ranges), for comparison
+    Bp = D.Batch(mats, Xs, Ys, 1.0, 0.0, workgroups=1024)
+    t_persist = epochs(lambda: Bp.run(use_graph=True), 10, 5)
+    Bp.destroy()
     T = info["model_bytes"]
     res = {"matrices": count, "rows": total_rows, "nnz": total_nnz, "tiles": info["ntiles"],
            "workgroups": info["workgroups"], "model_bytes": T,
            "graph_us": round(t_graph * 1e6, 1), "graph_gbs": round(T / t_graph / 1e9, 1),
            "direct_us": round(t_direct * 1e6, 1),
+           "persistent_1024_us": round(t_persist * 1e6, 1),
            "separate_us": round(t_sep * 1e6, 1), "separate_gbs": round(T / t_sep / 1e9, 1),
            "speedup_vs_separate": round(t_sep / t_graph, 3),
            "selector": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sel.items()}}

@@ -404,9 +404,10 @@ typedef struct damn_batch_s* damn_batch;
  * nrhs[i]) are device pointers, row-major like damn_spmm; the batch keeps
  * the pointers (not the data) and the handles' device arrays, which must
  * outlive it.  Rows are cut into tiles of at most max(2048, longest row)
- * entries (at most 4096) and the tile list is split into `workgroups`
- * contiguous ranges of about equal modelled bytes (0: 1024 workgroups).
- * The launch is captured once into a HIP graph.
+ * entries (at most 4096).  workgroups == 0: the launch has one workgroup
+ * per tile; workgroups > 0: a persistent grid of that many workgroups, each
+ * walking one of `workgroups` contiguous ranges of the tile list of about
+ * equal modelled bytes.  The launch is captured once into a HIP graph.
  * Errors: DAMN_ERR_INVALID_ARG (null, non-DA16 or non-float64 handle),
  *         DAMN_ERR_UNSUPPORTED (nrhs outside 1..8, a row longer than 4096
  *         entries), DAMN_ERR_ALLOC, DAMN_ERR_HIP. */

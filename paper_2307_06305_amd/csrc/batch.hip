@@ -2,14 +2,16 @@
 // right-hand sides, in one persistent launch captured in a HIP graph.
 //
 // At creation the host cuts every matrix into stream tiles (consecutive rows
-// holding at most `cap` entries), lists the tiles of all matrices in order,
-// and splits the list into contiguous ranges of about equal modelled bytes,
-// one range per workgroup.  The kernel walks its range; each tile is copied
-// from HBM into LDS with non-temporal 16-byte direct-to-LDS loads, then every
-// row is reduced by G lanes for all right-hand sides of its matrix at once
-// (X and Y row-major, the nrhs values of a row adjacent).  The static ranges
-// need no atomic work queue and no reset between launches, which keeps the
-// launch replayable from a graph.
+// holding at most `cap` entries) and lists the tiles of all matrices in
+// order.  By default the launch has one workgroup per tile and the hardware
+// dispatcher keeps every CU full; on request the list is instead split into
+// contiguous ranges of about equal modelled bytes, one per workgroup of a
+// persistent grid that walks its range.  Each tile is copied from HBM into
+// LDS with non-temporal 16-byte direct-to-LDS loads, then every row is
+// reduced by G lanes for all right-hand sides of its matrix at once (X and Y
+// row-major, the nrhs values of a row adjacent).  Neither mode needs an
+// atomic work queue or a reset between launches, which keeps the launch
+// replayable from a graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -77,8 +79,10 @@ __global__ __launch_bounds__(256) void batch_spmm(const BatchMat* __restrict__ m
   double* val_s = reinterpret_cast<double*>(lds);
   int16_t* idx_s = reinterpret_cast<int16_t*>(lds + sizeof(double) * (cap + 16));
   const uint32_t w = kern::xcd_contiguous(blockIdx.x, gridDim.x);
-  const int32_t t_end = range[w + 1];
-  for (int32_t t = range[w]; t < t_end; ++t) {
+  // range == nullptr: one tile per workgroup; else the workgroup's range
+  const int32_t t_begin = range ? range[w] : int32_t(w);
+  const int32_t t_end = range ? range[w + 1] : int32_t(w) + 1;
+  for (int32_t t = t_begin; t < t_end; ++t) {
     const BatchTile tile = tiles[t];
     const BatchMat m = mats[tile.mat];
     const int32_t p0 = m.rowptr[tile.r0], p1 = m.rowptr[tile.r1];
@@ -114,7 +118,7 @@ struct damn_batch_s {
   double alpha = 1.0, beta = 0.0;
   damn::bk::BatchMat* d_mats = nullptr;
   damn::bk::BatchTile* d_tiles = nullptr;
-  int32_t* d_range = nullptr;
+  int32_t* d_range = nullptr;  // null: one workgroup per tile
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -139,7 +143,8 @@ void free_batch(damn_batch B) {
 hipError_t launch_batch(damn_batch B, hipStream_t s) {
   if (B->ntiles == 0) return hipSuccess;
   const size_t shmem = size_t(B->cap + 16) * (sizeof(double) + sizeof(int16_t));
-  hipLaunchKernelGGL(bk::batch_spmm, dim3(uint32_t(B->workgroups)), dim3(256), shmem, s,
+  const uint32_t grid = B->d_range ? uint32_t(B->workgroups) : uint32_t(B->ntiles);
+  hipLaunchKernelGGL(bk::batch_spmm, dim3(grid), dim3(256), shmem, s,
                      B->d_mats, B->d_tiles, B->d_range, B->cap, B->alpha, B->beta,
                      int32_t(B->beta != 0.0));
   return hipGetLastError();
@@ -158,7 +163,6 @@ extern "C" int damn_batch_create(damn_batch* out, int32_t count, const damn_mat*
                                                     X == nullptr || Y == nullptr)))
     return DAMN_ERR_INVALID_ARG;
   if (workgroups < 0) return DAMN_ERR_INVALID_ARG;
-  if (workgroups == 0) workgroups = 1024;
   hipStream_t s = static_cast<hipStream_t>(stream);
   // tile cap: at least the longest row, rounded to 8 entries, 2048..4096
   int32_t longest = 0;
@@ -205,9 +209,9 @@ extern "C" int damn_batch_create(damn_batch* out, int32_t count, const damn_mat*
   }
   const int64_t nt = int64_t(ht.size());
   if (nt > INT32_MAX) return DAMN_ERR_UNSUPPORTED;
-  // contiguous ranges of about equal work
+  // persistent grid: contiguous ranges of about equal work
   std::vector<int32_t> range(size_t(workgroups) + 1, int32_t(nt));
-  {
+  if (workgroups > 0) {
     double tw = 0;
     for (double v : work) tw += v;
     const double per = tw / workgroups;
@@ -225,7 +229,7 @@ extern "C" int damn_batch_create(damn_batch* out, int32_t count, const damn_mat*
   if (!B) return DAMN_ERR_ALLOC;
   hipGetDevice(&B->device);
   B->count = count;
-  B->workgroups = workgroups;
+  B->workgroups = workgroups > 0 ? workgroups : int32_t(nt);
   B->cap = cap;
   B->ntiles = nt;
   B->alpha = alpha;
@@ -238,7 +242,8 @@ extern "C" int damn_batch_create(damn_batch* out, int32_t count, const damn_mat*
   }
   if (hipMalloc(&B->d_mats, sizeof(bk::BatchMat) * std::max<size_t>(hm.size(), 1)) != hipSuccess ||
       hipMalloc(&B->d_tiles, sizeof(bk::BatchTile) * std::max<size_t>(ht.size(), 1)) != hipSuccess ||
-      hipMalloc(&B->d_range, sizeof(int32_t) * range.size()) != hipSuccess) {
+      (workgroups > 0 &&
+       hipMalloc(&B->d_range, sizeof(int32_t) * range.size()) != hipSuccess)) {
     free_batch(B);
     return DAMN_ERR_ALLOC;
   }
@@ -246,8 +251,9 @@ extern "C" int damn_batch_create(damn_batch* out, int32_t count, const damn_mat*
                                           hipMemcpyHostToDevice, s) == hipSuccess) &&
             (ht.empty() || hipMemcpyAsync(B->d_tiles, ht.data(), sizeof(bk::BatchTile) * ht.size(),
                                           hipMemcpyHostToDevice, s) == hipSuccess) &&
-            hipMemcpyAsync(B->d_range, range.data(), sizeof(int32_t) * range.size(),
-                           hipMemcpyHostToDevice, s) == hipSuccess &&
+            (workgroups == 0 ||
+             hipMemcpyAsync(B->d_range, range.data(), sizeof(int32_t) * range.size(),
+                            hipMemcpyHostToDevice, s) == hipSuccess) &&
             hipStreamSynchronize(s) == hipSuccess;
   // capture the launch once into a graph, on a stream of our own
   hipStream_t cs = nullptr;

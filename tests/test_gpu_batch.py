@@ -47,14 +47,16 @@ def _expect(A, e, X, Yprev, alpha, beta):
     return Y, bounds
 
 
-@pytest.mark.parametrize("workgroups", [37, 1024])
+@pytest.mark.parametrize("workgroups", [0, 37, 1024])
 def test_batch_direct_matches_oracle(workgroups):
     torch = torch_or_skip()
     alpha, beta = 1.5, -0.5
     mats, Xs, Ys, Y0s, data = _setup(torch, 48, 7)
     B = D.Batch(mats, Xs, Ys, alpha, beta, workgroups=workgroups)
     info = B.info()
-    assert info["workgroups"] == workgroups and info["ntiles"] > 0
+    assert info["ntiles"] > 0
+    # 0: one workgroup per tile; else a persistent grid of that size
+    assert info["workgroups"] == (workgroups or info["ntiles"])
     B.run(use_graph=False)
     for i, (A, e, X) in enumerate(data):
         Y, bounds = _expect(A, e, X, Y0s[i], alpha, beta)
@@ -64,11 +66,12 @@ def test_batch_direct_matches_oracle(workgroups):
     B.destroy()
 
 
-def test_batch_graph_replays_match_oracle():
+@pytest.mark.parametrize("workgroups", [0, 256])
+def test_batch_graph_replays_match_oracle(workgroups):
     torch = torch_or_skip()
     alpha, beta = 0.75, 0.5
     mats, Xs, Ys, Y0s, data = _setup(torch, 24, 11)
-    B = D.Batch(mats, Xs, Ys, alpha, beta, workgroups=256)
+    B = D.Batch(mats, Xs, Ys, alpha, beta, workgroups=workgroups)
     prev = [y.copy() for y in Y0s]
     scratch = torch.randn(512, 512, device="cuda", dtype=torch.float32)
     for replay in range(3):

@@ -35,22 +35,29 @@ struct BatchMat {
   int32_t nrows;
   int32_t nrhs;
   int32_t lanes;
-  int32_t pad;
+  int32_t pairs;  // X and Y 16-byte aligned and nrhs even: move values in pairs
 };
+
+constexpr int32_t kBatchTileRows = 256;
 
 struct BatchTile {
   int32_t mat, r0, r1, pad;
 };
 
-template <int NRHS>
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+// PAIRS: X and Y rows are read and written as 16-byte pairs (NRHS even,
+// both 16-byte aligned).
+template <int NRHS, bool PAIRS>
 __device__ __forceinline__ void tile_rows(const BatchMat& m, int32_t r0, int32_t r1, int32_t a0,
-                                          const double* __restrict__ val_s,
-                                          const int16_t* __restrict__ idx_s, double alpha,
+                                          int32_t ar, const double* __restrict__ val_s,
+                                          const int16_t* __restrict__ idx_s,
+                                          const int32_t* __restrict__ rp_s, double alpha,
                                           double beta, bool read_y) {
   const int G = m.lanes;
   const int lane = int(threadIdx.x) % G;
   for (int32_t r = r0 + int32_t(threadIdx.x) / G; r < r1; r += 256 / G) {
-    const int32_t s = m.rowptr[r] - a0, e = m.rowptr[r + 1] - a0;
+    const int32_t s = rp_s[r - ar] - a0, e = rp_s[r + 1 - ar] - a0;
     const double* Xs = m.X + int64_t(r) * NRHS;
     double acc[NRHS];
 #pragma unroll
@@ -58,15 +65,34 @@ __device__ __forceinline__ void tile_rows(const BatchMat& m, int32_t r0, int32_t
     for (int32_t k = s + lane; k < e; k += G) {
       const double v = val_s[k];
       const double* xr = Xs + int64_t(idx_s[k]) * NRHS;
+      if (PAIRS) {
 #pragma unroll
-      for (int j = 0; j < NRHS; ++j) acc[j] += v * xr[j];
+        for (int j = 0; j < NRHS / 2; ++j) {
+          const d2 xv = reinterpret_cast<const d2*>(xr)[j];
+          acc[2 * j] += v * xv.x;
+          acc[2 * j + 1] += v * xv.y;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < NRHS; ++j) acc[j] += v * xr[j];
+      }
     }
 #pragma unroll
     for (int j = 0; j < NRHS; ++j) acc[j] = kern::group_sum(acc[j], G);
     if (lane == 0) {
       double* yr = m.Y + int64_t(r) * NRHS;
+      if (PAIRS) {
 #pragma unroll
-      for (int j = 0; j < NRHS; ++j) yr[j] = kern::finish(acc[j], alpha, beta, read_y, yr + j);
+        for (int j = 0; j < NRHS / 2; ++j) {
+          d2 out;
+          out.x = kern::finish(acc[2 * j], alpha, beta, read_y, yr + 2 * j);
+          out.y = kern::finish(acc[2 * j + 1], alpha, beta, read_y, yr + 2 * j + 1);
+          reinterpret_cast<d2*>(yr)[j] = out;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < NRHS; ++j) yr[j] = kern::finish(acc[j], alpha, beta, read_y, yr + j);
+      }
     }
   }
 }
@@ -78,6 +104,7 @@ __global__ __launch_bounds__(256) void batch_spmm(const BatchMat* __restrict__ m
   extern __shared__ __align__(16) unsigned char lds[];
   double* val_s = reinterpret_cast<double*>(lds);
   int16_t* idx_s = reinterpret_cast<int16_t*>(lds + sizeof(double) * (cap + 16));
+  int32_t* rp_s = reinterpret_cast<int32_t*>(lds + (sizeof(double) + sizeof(int16_t)) * (cap + 16));
   const uint32_t w = kern::xcd_contiguous(blockIdx.x, gridDim.x);
   // range == nullptr: one tile per workgroup; else the workgroup's range
   const int32_t t_begin = range ? range[w] : int32_t(w);
@@ -90,18 +117,26 @@ __global__ __launch_bounds__(256) void batch_spmm(const BatchMat* __restrict__ m
     __syncthreads();  // the previous tile's readers are done with LDS
     kern::copy_to_lds(val_s, m.val, a0, p1 - a0);
     kern::copy_to_lds(idx_s, m.off, a0, p1 - a0);
+    // the tile's row pointers rowptr[ar .. r1] (at most kBatchTileRows + 4;
+    // the allocation is padded for the last piece)
+    const int32_t ar = tile.r0 & ~3;
+    kern::copy_to_lds(rp_s, m.rowptr, ar, tile.r1 + 1 - ar);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
+#define DAMN_ROWS(K, P) \
+  tile_rows<K, P>(m, tile.r0, tile.r1, a0, ar, val_s, idx_s, rp_s, alpha, beta, read_y)
+    const bool pairs = m.pairs != 0;
     switch (m.nrhs) {
-      case 1: tile_rows<1>(m, tile.r0, tile.r1, a0, val_s, idx_s, alpha, beta, read_y); break;
-      case 2: tile_rows<2>(m, tile.r0, tile.r1, a0, val_s, idx_s, alpha, beta, read_y); break;
-      case 3: tile_rows<3>(m, tile.r0, tile.r1, a0, val_s, idx_s, alpha, beta, read_y); break;
-      case 4: tile_rows<4>(m, tile.r0, tile.r1, a0, val_s, idx_s, alpha, beta, read_y); break;
-      case 5: tile_rows<5>(m, tile.r0, tile.r1, a0, val_s, idx_s, alpha, beta, read_y); break;
-      case 6: tile_rows<6>(m, tile.r0, tile.r1, a0, val_s, idx_s, alpha, beta, read_y); break;
-      case 7: tile_rows<7>(m, tile.r0, tile.r1, a0, val_s, idx_s, alpha, beta, read_y); break;
-      default: tile_rows<8>(m, tile.r0, tile.r1, a0, val_s, idx_s, alpha, beta, read_y); break;
+      case 1: DAMN_ROWS(1, false); break;
+      case 2: if (pairs) DAMN_ROWS(2, true); else DAMN_ROWS(2, false); break;
+      case 3: DAMN_ROWS(3, false); break;
+      case 4: if (pairs) DAMN_ROWS(4, true); else DAMN_ROWS(4, false); break;
+      case 5: DAMN_ROWS(5, false); break;
+      case 6: if (pairs) DAMN_ROWS(6, true); else DAMN_ROWS(6, false); break;
+      case 7: DAMN_ROWS(7, false); break;
+      default: if (pairs) DAMN_ROWS(8, true); else DAMN_ROWS(8, false); break;
     }
+#undef DAMN_ROWS
   }
 }
 
@@ -142,7 +177,8 @@ void free_batch(damn_batch B) {
 
 hipError_t launch_batch(damn_batch B, hipStream_t s) {
   if (B->ntiles == 0) return hipSuccess;
-  const size_t shmem = size_t(B->cap + 16) * (sizeof(double) + sizeof(int16_t));
+  const size_t shmem = size_t(B->cap + 16) * (sizeof(double) + sizeof(int16_t)) +
+                       sizeof(int32_t) * (bk::kBatchTileRows + 16);
   const uint32_t grid = B->d_range ? uint32_t(B->workgroups) : uint32_t(B->ntiles);
   hipLaunchKernelGGL(bk::batch_spmm, dim3(grid), dim3(256), shmem, s,
                      B->d_mats, B->d_tiles, B->d_range, B->cap, B->alpha, B->beta,
@@ -188,13 +224,16 @@ extern "C" int damn_batch_create(damn_batch* out, int32_t count, const damn_mat*
       const damn_mat A = mats[i];
       const int32_t k = nrhs[i];
       const int32_t lanes = A->cfg.variant == DAMN_VAR_STREAM ? std::min(A->cfg.lanes, 16) : 2;
+      const bool aligned = ((reinterpret_cast<uintptr_t>(X[i]) |
+                             reinterpret_cast<uintptr_t>(Y[i])) & 15) == 0;
       hm[i] = {A->d_rowptr, static_cast<const int16_t*>(A->d_idx),
-               static_cast<const double*>(A->d_val), X[i], Y[i], A->nrows, k, lanes, 0};
+               static_cast<const double*>(A->d_val), X[i], Y[i], A->nrows, k, lanes,
+               int32_t(aligned && k % 2 == 0)};
       const int32_t* rp = A->h_rowptr.data();
       int32_t r = 0;
       while (r < A->nrows) {
         const int32_t first = r;
-        while (r < A->nrows && r - first < 256 && rp[r + 1] - rp[first] <= cap) ++r;
+        while (r < A->nrows && r - first < bk::kBatchTileRows && rp[r + 1] - rp[first] <= cap) ++r;
         ht.push_back({i, first, r, 0});
         const double bytes = double(rp[r] - rp[first]) * (2 + 8) +
                              double(r - first) * (4 + 8.0 * k * (beta != 0.0 ? 2 : 1)) +

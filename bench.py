@@ -552,6 +552,9 @@ def bench_batch(D, args):
             default.append(S.config_class(default_cfg, k))
         sum_best += float(np.min(times[-1]))  # this matrix's own product, best class
     sel = S.evaluate(S.load_weights(), np.array(feats), np.array(times), np.array(default))
+    sel["with_autotuner_fallback"] = [
+        S.evaluate_fallback(S.load_weights(), np.array(feats), np.array(times), th)
+        for th in (0.1, 0.2, 0.3, 0.5)]
     log(f"selector on the batch matrices: {sel}")
 
     def separate():
@@ -588,6 +591,8 @@ def bench_batch(D, args):
            "sum_of_tuned_kernel_us": round(sum_best * 1e6, 1),
            "speedup_vs_separate": round(t_sep / t_graph, 3),
            "selector": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sel.items()}}
+    res["selector"]["with_autotuner_fallback"] = [
+        {k: round(v, 4) for k, v in fb.items()} for fb in sel["with_autotuner_fallback"]]
     log(f"batch: {res}")
     B.destroy()
     for M in mats:

@@ -496,6 +496,12 @@ int damn_mlp_train(damn_mlp M, int32_t N, const float* feats, const float* times
  * kernel: the most probable class that applies to the row's nrhs. */
 int damn_select(damn_mlp M, int32_t N, const float* feats, int32_t* cls, void* stream);
 
+/* damn_select, plus prob[N] (host): the probability the network gives the
+ * chosen class under the softmax over the applicable classes.  A caller
+ * falls back to damn_autotune when it is low. */
+int damn_select_prob(damn_mlp M, int32_t N, const float* feats, int32_t* cls, float* prob,
+                     void* stream);
+
 /* ------------------------------------------------------------------------
  * Measurement helpers.
  * --------------------------------------------------------------------- */

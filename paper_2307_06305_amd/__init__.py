@@ -583,12 +583,17 @@ class Mlp:
                "mlp_train")
         return losses
 
-    def select(self, feats, stream=None):
+    def select(self, feats, stream=None, with_prob=False):
+        """Most probable applicable class per feature row; with_prob also
+        returns the probability the network gives it."""
         F = np.ascontiguousarray(np.atleast_2d(feats), dtype=np.float32)
         out = np.empty(F.shape[0], dtype=np.int32)
-        _check(lib.damn_select(self._h, F.shape[0], F.ctypes.data_as(C.c_void_p),
-                               out.ctypes.data_as(C.c_void_p), _stream_ptr(stream)), "select")
-        return out
+        prob = np.empty(F.shape[0], dtype=np.float32)
+        _check(lib.damn_select_prob(self._h, F.shape[0], F.ctypes.data_as(C.c_void_p),
+                                    out.ctypes.data_as(C.c_void_p),
+                                    prob.ctypes.data_as(C.c_void_p) if with_prob else None,
+                                    _stream_ptr(stream)), "select")
+        return (out, prob) if with_prob else out
 
     def destroy(self):
         if self._h is not None and self._h.value:

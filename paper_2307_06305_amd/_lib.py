@@ -97,6 +97,7 @@ _SIGS = {
     "damn_mlp_train": (C.c_int, [_vp, _i32, _vp, _vp, _i32, _i32, C.c_float, C.c_float,
                                  C.c_uint64, _vp, _vp]),
     "damn_select": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
+    "damn_select_prob": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
 }
 
 class _Lib:

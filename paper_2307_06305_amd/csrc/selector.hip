@@ -189,9 +189,12 @@ __global__ void add_loss(const float* __restrict__ loss, int32_t B, float* __res
 }
 
 // inference: most probable valid class (lowest index on ties)
+// The most probable applicable class of each row, and (prob != nullptr) its
+// probability under the softmax over the applicable classes.
 __global__ __launch_bounds__(64) void select_cls(const float* __restrict__ P,
                                                  const float* __restrict__ feats,
-                                                 int32_t* __restrict__ out) {
+                                                 int32_t* __restrict__ out,
+                                                 float* __restrict__ prob) {
   __shared__ float xs[F], h1[H], h2[H], z[H];
   const int s = blockIdx.x;
   const float* f = feats + int64_t(s) * F;
@@ -201,6 +204,12 @@ __global__ __launch_bounds__(64) void select_cls(const float* __restrict__ P,
     for (int k = 0; k < K; ++k)
       if (class_valid(k, f[9]) && (best < 0 || z[k] > z[best])) best = k;
     out[s] = best;
+    if (prob) {
+      float sum = 0.0f;
+      for (int k = 0; k < K; ++k)
+        if (class_valid(k, f[9])) sum += expf(z[k] - z[best]);
+      prob[s] = 1.0f / sum;
+    }
   }
 }
 
@@ -554,32 +563,42 @@ int damn_mlp_train(damn_mlp M, int32_t N, const float* feats, const float* times
   return DAMN_OK;
 }
 
-int damn_select(damn_mlp M, int32_t N, const float* feats, int32_t* cls, void* stream) {
+int damn_select_prob(damn_mlp M, int32_t N, const float* feats, int32_t* cls, float* prob,
+                     void* stream) {
   if (M == nullptr || N < 0 || (N > 0 && (feats == nullptr || cls == nullptr)))
     return DAMN_ERR_INVALID_ARG;
   if (N == 0) return DAMN_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   float* df = nullptr;
   int32_t* dc = nullptr;
+  float* dp = nullptr;
   int st = DAMN_OK;
   if (hipMalloc(&df, sizeof(float) * size_t(N) * sel::F) != hipSuccess ||
-      hipMalloc(&dc, sizeof(int32_t) * N) != hipSuccess)
+      hipMalloc(&dc, sizeof(int32_t) * N) != hipSuccess ||
+      (prob && hipMalloc(&dp, sizeof(float) * N) != hipSuccess))
     st = DAMN_ERR_ALLOC;
   if (st == DAMN_OK) {
     bool ok = hipMemcpyAsync(df, feats, sizeof(float) * size_t(N) * sel::F,
                              hipMemcpyHostToDevice, s) == hipSuccess;
     if (ok) {
-      hipLaunchKernelGGL(sel::select_cls, dim3(N), dim3(64), 0, s, M->P, df, dc);
+      hipLaunchKernelGGL(sel::select_cls, dim3(N), dim3(64), 0, s, M->P, df, dc, dp);
       ok = hipGetLastError() == hipSuccess &&
            hipMemcpyAsync(cls, dc, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s) ==
                hipSuccess &&
+           (!prob || hipMemcpyAsync(prob, dp, sizeof(float) * N, hipMemcpyDeviceToHost, s) ==
+                         hipSuccess) &&
            hipStreamSynchronize(s) == hipSuccess;
     }
     if (!ok) st = DAMN_ERR_HIP;
   }
   if (df) hipFree(df);
   if (dc) hipFree(dc);
+  if (dp) hipFree(dp);
   return st;
+}
+
+int damn_select(damn_mlp M, int32_t N, const float* feats, int32_t* cls, void* stream) {
+  return damn_select_prob(M, N, feats, cls, nullptr, stream);
 }
 
 int damn_mlp_destroy(damn_mlp M) {

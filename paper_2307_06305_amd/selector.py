@@ -115,6 +115,42 @@ def evaluate(params, F, T, default):
             "time_ratio_default_over_selected": float((T[idx, default]).sum() / T[idx, cls].sum())}
 
 
+def evaluate_fallback(params, F, T, threshold):
+    """The selector with the exhaustive autotuner behind it: rows whose
+    chosen class has probability below `threshold` are autotuned (regret 0,
+    the autotuner's choice is the fastest measured class), the rest take the
+    network's choice."""
+    net = Mlp(params)
+    cls, prob = net.select(F, with_prob=True)
+    net.destroy()
+    idx = np.arange(len(F))
+    reg = T[idx, cls] / T.min(axis=1) - 1.0
+    fb = prob < threshold
+    reg = np.where(fb, 0.0, reg)
+    return {"threshold": float(threshold), "fallback_fraction": float(fb.mean()),
+            "mean_regret": float(reg.mean()), "p95_regret": float(np.quantile(reg, 0.95)),
+            "within_5pct": float(np.mean(reg <= 0.05))}
+
+
+def choose(net, A, M, nrhs, X, Y, threshold=0.2, reps=3):
+    """Configure handle M for its product with nrhs right-hand sides: the
+    network's class when its probability reaches `threshold`, else the
+    exhaustive autotuner's (which times every class on X, Y and overwrites
+    Y).  A: the host CSR arrays of M's matrix (for the features).  Returns
+    (class, probability, autotuned)."""
+    from . import class_config, features
+
+    f = features(A.nrows, A.ncols, A.rowptr, A.colids, nrhs)
+    cls, prob = net.select(f, with_prob=True)
+    cls, prob = int(cls[0]), float(prob[0])
+    if prob < threshold:
+        t = autotune(M, nrhs, X, Y, reps=reps)
+        return int(np.argmin(t)), prob, True
+    v, lanes, unroll, tile, _ = class_config(cls)
+    M.set_config(v, lanes, unroll, tile)
+    return cls, prob, False
+
+
 def load_weights(path=WEIGHTS):
     p = np.load(path, allow_pickle=False)
     if p.shape != (MLP_NPARAMS,) or p.dtype != np.float32:

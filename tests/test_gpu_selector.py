@@ -144,3 +144,38 @@ def test_shipped_selector_beats_the_default_on_unseen_matrices():
     assert res["mean_regret"] < res["default_mean_slowdown"]
     assert res["time_ratio_default_over_selected"] > 1.0
     assert res["mean_regret"] <= 0.10
+
+
+def test_select_probability_matches_oracle_softmax():
+    torch_or_skip()
+    p = _params(8)
+    F, _ = _batch(200, 9)
+    net = D.Mlp(p)
+    cls, prob = net.select(F, with_prob=True)
+    net.destroy()
+    P = OM.unpack(p.astype(np.float64), K)
+    mask = _mask(F)
+    Z = np.where(mask, OM.forward(P, F.astype(np.float64), mask)["Z"], -np.inf)
+    ez = np.exp(Z - Z.max(axis=1, keepdims=True))
+    ref = (ez / ez.sum(axis=1, keepdims=True))[np.arange(len(F)), cls]
+    assert np.all(np.abs(prob - ref) <= 1e-4 * ref + 1e-6)
+    assert np.all((prob > 0) & (prob <= 1.0 + 1e-6))
+
+
+def test_choose_falls_back_to_the_autotuner():
+    """Below the probability threshold the exhaustive autotuner configures
+    the handle; above it the network's class is set."""
+    torch = torch_or_skip()
+    d = batch_member(12, 3, n_lo=2e4, n_hi=4e4)
+    A = batch_matrix(d)
+    e = D.encode(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, allow_rcm=False)
+    M = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], e["vals"])
+    x = dev(np.ones(A.ncols))
+    y = torch.zeros(A.nrows, dtype=torch.float64, device="cuda")
+    net = S.load_net()
+    cls, prob, tuned = S.choose(net, A, M, 1, x, y, threshold=0.0)
+    assert not tuned and S.config_class(M.get_config(), 1) == cls
+    cls2, prob2, tuned2 = S.choose(net, A, M, 1, x, y, threshold=1.01)
+    assert tuned2 and prob2 == prob and S.config_class(M.get_config(), 1) == cls2
+    net.destroy()
+    M.destroy()

@@ -474,6 +474,49 @@ def bench_blocks(D, args):
     return out
 
 
+def bench_spmm(D, args):
+    """SpMM Y = A X with nrhs = 1, 2, 4, 8 interleaved right-hand sides on the
+    27-point 128^3 matrix, DA-CSR and CSR: each index and value is read
+    once for all right-hand sides."""
+    import numpy as np
+    import torch
+
+    from workloads import config_matrix
+
+    A = config_matrix(1)
+    e = D.encode(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, allow_rcm=False)
+    M = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], e["vals"])
+    Cm = D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals)
+    g = torch.Generator().manual_seed(2101)
+    out = {"workload": "stencil3d_27pt_128^3"}
+    for k in (1, 2, 4, 8):
+        X = (torch.rand(A.ncols, k, generator=g, dtype=torch.float64) * 2 - 1).to("cuda")
+        Y = torch.zeros(A.nrows, k, dtype=torch.float64, device="cuda")
+        row = {}
+        for name, mat, ib in (("da", M, 2), ("csr", Cm, 4)):
+            T = model_bytes(A.nrows, A.ncols, A.nnz, ib, nrhs=k)
+            row[name] = {"model_bytes": T}
+            for vname, variant in (("stream", D.VAR_STREAM), ("vector", D.VAR_VECTOR)):
+                t_best = None
+                for lanes in (1, 2, 4, 8, 16):
+                    mat.set_config(variant, lanes, 1, 2048)
+                    mat.spmm(X, Y)
+                    t = epochs(lambda: mat.spmm(X, Y), 10, 3)
+                    if t_best is None or t < t_best[0]:
+                        t_best = (t, lanes)
+                row[name][vname] = {"us": round(t_best[0] * 1e6, 1), "lanes": t_best[1],
+                                    "gbs": round(T / t_best[0] / 1e9, 1)}
+            best = min(row[name]["stream"]["us"], row[name]["vector"]["us"])
+            row[name]["us"] = best
+            row[name]["gbs"] = round(T / (best * 1e-6) / 1e9, 1)
+        row["speedup"] = round(row["csr"]["us"] / row["da"]["us"], 4)
+        out[f"nrhs{k}"] = row
+        log(f"spmm nrhs={k}: {row}")
+    M.destroy()
+    Cm.destroy()
+    return out
+
+
 def bench_coo(D, args):
     """DA-COO against COO (Sec. 1: diagonal addressing applied to one index
     vector of COO) on the 27-point 128^3 matrix; both stream a 4-byte row
@@ -638,6 +681,7 @@ def main():
                     help="skip the index / scalar width grid and the non-square products")
     ap.add_argument("--skip-blocks", action="store_true", help="skip the DA-BSR / BSR products")
     ap.add_argument("--skip-coo", action="store_true", help="skip the DA-COO / COO products")
+    ap.add_argument("--skip-spmm", action="store_true", help="skip the SpMM products")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-workgroups", type=int, default=0)
     ap.add_argument("--profile", action="store_true",
@@ -797,6 +841,8 @@ def main():
         res["grid"] = bench_grid(D, args)
     if not args.skip_blocks:
         res["blocks"] = bench_blocks(D, args)
+    if not args.skip_spmm:
+        res["spmm"] = bench_spmm(D, args)
     if not args.skip_coo:
         res["coo"] = bench_coo(D, args)
     if not args.skip_batch:

@@ -314,7 +314,10 @@ int damn_csr_spmv(damn_mat A, const void* x, void* y, double alpha,
 
 /* Y <- alpha*A*X + beta*Y for nrhs right-hand sides, 1 <= nrhs <= 8.
  * X is ncols x nrhs and Y is nrows x nrhs, both row-major (the nrhs values
- * of one row are adjacent).  Float64 DA16 and CSR32 handles.
+ * of one row are adjacent).  Float64 DA16 and CSR32 handles.  The handle's
+ * configuration picks the kernel: the stream variant (tiles in LDS, `lanes`
+ * lanes per row accumulating all nrhs sums) or the vector variant.
+ * alpha == 0 scales Y by beta without reading A or X.
  * Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_UNSUPPORTED (nrhs > 8, another
  *         format or scalar type). */
 int damn_spmm(damn_mat A, const void* X, void* Y, int32_t nrhs, double alpha,
@@ -453,7 +456,8 @@ int damn_features(int32_t nrows, int32_t ncols, const int32_t* rowptr,
 /* Configuration of class cls (0 <= cls < DAMN_NCLASS): classes 0..20 are
  * the vector variant (lanes 1..64 x unroll 1,2,4), 21..41 the stream variant
  * (lanes 1..64 x tile 1024, 2048, 4096), both for nrhs = 1; 42..48 are SpMM
- * lane counts 1..64 for nrhs > 1 (*spmm = 1). */
+ * lane counts 1..64 of the stream SpMM with 2048-entry tiles, for nrhs > 1
+ * (*spmm = 1). */
 int damn_class_config(int32_t cls, damn_config* cfg, int32_t* spmm);
 
 /* Time every class that applies to nrhs (reps launches each after one

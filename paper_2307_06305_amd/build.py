@@ -22,8 +22,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdamn.so")
 
 ARCH = "gfx950"
-HIP_SOURCES = ["spmv_kernels.hip", "spmv_grid.hip", "spmv_bsr.hip", "spmv_coo.hip", "api.hip",
-               "cg.hip", "batch.hip", "selector.hip"]
+HIP_SOURCES = ["spmv_kernels.hip", "spmv_grid.hip", "spmv_bsr.hip", "spmv_coo.hip",
+               "spmm_stream.hip", "api.hip", "cg.hip", "batch.hip", "selector.hip"]
 CPP_SOURCES = ["host_format.cpp", "host_grid.cpp", "host_blocks.cpp", "host_rcm.cpp",
                "host_features.cpp"]
 

@@ -482,6 +482,23 @@ int damn_spmm(damn_mat A, const void* X, void* Y, int32_t nrhs, double alpha, do
   a.format = A->format;
   a.store = A->dtype;
   a.stream = static_cast<hipStream_t>(stream);
+  if (alpha == 0.0) {  // Y <- beta*Y over nrows*nrhs values; A and X are not read
+    if (int64_t(A->nrows) * nrhs > INT32_MAX) return DAMN_ERR_UNSUPPORTED;
+    a.nrows = int32_t(int64_t(A->nrows) * nrhs);
+    const hipError_t e = launch_spmv(a, DAMN_VAR_VECTOR, 1, 1);
+    return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
+  }
+  if (A->cfg.variant == DAMN_VAR_STREAM) {
+    // one right-hand side: the SpMV kernels (X and Y are vectors)
+    if (nrhs == 1) return run_spmv(A, X, Y, alpha, beta, stream, format_is_da(A->format));
+    const int st = build_tiles(A, A->cfg.tile);
+    if (st != DAMN_OK) return st;
+    a.tile_row = A->d_tiles;
+    a.ntiles = A->ntiles;
+    a.cap = A->tiles_cap;
+    const hipError_t e = launch_spmm_stream(a, A->cfg.lanes, nrhs);
+    return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
+  }
   const hipError_t e = launch_spmm(a, A->cfg.lanes, nrhs);
   return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
 }

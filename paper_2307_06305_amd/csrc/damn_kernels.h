@@ -70,8 +70,10 @@ hipError_t launch_spmv_coo(const SpmvArgs& a);
 // lanes in {1, 2, 4, 8, 16}; alpha != 0; DA16 or CSR32, float64 or float32.
 hipError_t launch_spmv_dot(const SpmvArgs& a, int lanes, const void* w, double* partial,
                            const int32_t* done);
-// float64 DA16 or CSR32 only; 1 <= nrhs <= 8
+// float64 DA16 or CSR32 only; 1 <= nrhs <= 8; vector variant
 hipError_t launch_spmm(const SpmvArgs& a, int lanes, int nrhs);
+// The same with the stream variant's tiles (spmm_stream.hip)
+hipError_t launch_spmm_stream(const SpmvArgs& a, int lanes, int nrhs);
 hipError_t launch_stream_read(const void* src, int64_t bytes, double* sink, hipStream_t s);
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
 

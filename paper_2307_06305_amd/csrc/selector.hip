@@ -328,7 +328,7 @@ int damn_class_config(int32_t cls, damn_config* cfg, int32_t* spmm) {
     c.unroll = 1;
     c.tile = sel::kTiles[(cls - 21) % 3];
   } else {
-    c.variant = DAMN_VAR_VECTOR;
+    c.variant = DAMN_VAR_STREAM;  // the stream SpMM, 2048-entry tiles
     c.lanes = sel::kLanes[cls - 42];
     c.unroll = 1;
     c.tile = 2048;

@@ -182,10 +182,28 @@ def test_empty_shapes():
         C.destroy()
 
 
+SPMM_CFGS = ([(D.VAR_VECTOR, lanes, 2048) for lanes in (1, 4, 8, 32, 64)]
+             + [(D.VAR_STREAM, lanes, tile) for lanes in (1, 2, 4, 8, 16, 32, 64)
+                for tile in (1024, 4096)])
+
+
+def _dev_offset(a, offset):
+    """A contiguous device copy of a whose data starts `offset` float64 past
+    an allocation's start (offset 1: 8-byte but not 16-byte aligned)."""
+    import torch
+
+    flat = torch.zeros(a.size + offset, dtype=torch.float64, device="cuda")
+    flat[offset:] = torch.from_numpy(np.ascontiguousarray(a).ravel()).to("cuda")
+    return flat[offset:].view(*a.shape)
+
+
 @pytest.mark.parametrize("fmt", ["da", "csr"])
-@pytest.mark.parametrize("A", MATS[:4], ids=lambda A: A.name)
+@pytest.mark.parametrize("A", MATS, ids=lambda A: A.name)
 def test_spmm_matches_oracle(A, fmt):
-    torch = torch_or_skip()
+    """Both SpMM variants, every lane count, two tile sizes, aligned and
+    unaligned operands (16-byte pairs or single values)."""
+    torch_or_skip()
+    print(f"case {A.name} {fmt}", flush=True)
     e = _encode(A)
     M = (D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], A.vals) if fmt == "da"
          else D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals))
@@ -194,15 +212,32 @@ def test_spmm_matches_oracle(A, fmt):
         Y0 = uniform_vector(A.nrows, 20 + nrhs, nrhs)
         for alpha, beta in ((1.0, 0.0), (2.0, -1.0)):
             ref = OS.spmm_csr(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, X, alpha, beta, Y0)
-            for lanes in (1, 4, 8, 32, 64):
-                M.set_config(0, lanes, 1, 2048)
-                Yd = dev(Y0)
-                M.spmm(dev(X), Yd, alpha, beta)
-                Y = host(Yd)
-                for j in range(nrhs):
-                    bnd = error_bound(A.nrows, A.rowptr, A.colids, A.vals, X[:, j], alpha, beta,
-                                      Y0[:, j], U64)
-                    assert_within(Y[:, j], ref[:, j], bnd, f"{A.name} nrhs={nrhs} lanes={lanes}")
+            bnds = [error_bound(A.nrows, A.rowptr, A.colids, A.vals, X[:, j], alpha, beta,
+                                Y0[:, j], U64) for j in range(nrhs)]
+            for variant, lanes, tile in SPMM_CFGS:
+                for offset in ((0, 1) if nrhs % 2 == 0 else (0,)):
+                    M.set_config(variant, lanes, 1, tile)
+                    Yd = _dev_offset(Y0, offset)
+                    M.spmm(_dev_offset(X, offset), Yd, alpha, beta)
+                    Y = host(Yd)
+                    for j in range(nrhs):
+                        assert_within(Y[:, j], ref[:, j], bnds[j],
+                                      f"{A.name} nrhs={nrhs} v={variant} lanes={lanes} "
+                                      f"tile={tile} offset={offset}")
+    M.destroy()
+
+
+def test_spmm_alpha_zero_reads_neither_matrix_nor_x():
+    torch = torch_or_skip()
+    A = MATS[1]
+    e = _encode(A)
+    M = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], A.vals)
+    X = torch.full((A.ncols, 3), float("nan"), dtype=torch.float64, device="cuda")
+    for variant in (D.VAR_VECTOR, D.VAR_STREAM):
+        M.set_config(variant, 2, 1, 2048)
+        Y = torch.full((A.nrows, 3), 2.0, dtype=torch.float64, device="cuda")
+        M.spmm(X, Y, 0.0, -0.5)
+        assert np.all(host(Y) == -1.0)
     M.destroy()
 
 

@@ -59,24 +59,35 @@ __device__ __forceinline__ void tile_rows(const BatchMat& m, int32_t r0, int32_t
   for (int32_t r = r0 + int32_t(threadIdx.x) / G; r < r1; r += 256 / G) {
     const int32_t s = rp_s[r - ar] - a0, e = rp_s[r + 1 - ar] - a0;
     const double* Xs = m.X + int64_t(r) * NRHS;
-    double acc[NRHS];
+    // up to 4 right-hand sides, two entries in flight per lane
+    double acc[NRHS], acc2[NRHS];
 #pragma unroll
-    for (int j = 0; j < NRHS; ++j) acc[j] = 0.0;
-    for (int32_t k = s + lane; k < e; k += G) {
+    for (int j = 0; j < NRHS; ++j) acc[j] = acc2[j] = 0.0;
+    auto add = [&](double* a, int32_t k) {
       const double v = val_s[k];
       const double* xr = Xs + int64_t(idx_s[k]) * NRHS;
       if (PAIRS) {
 #pragma unroll
         for (int j = 0; j < NRHS / 2; ++j) {
           const d2 xv = reinterpret_cast<const d2*>(xr)[j];
-          acc[2 * j] += v * xv.x;
-          acc[2 * j + 1] += v * xv.y;
+          a[2 * j] += v * xv.x;
+          a[2 * j + 1] += v * xv.y;
         }
       } else {
 #pragma unroll
-        for (int j = 0; j < NRHS; ++j) acc[j] += v * xr[j];
+        for (int j = 0; j < NRHS; ++j) a[j] += v * xr[j];
+      }
+    };
+    int32_t k = s + lane;
+    if (NRHS <= 4) {
+      for (; k + G < e; k += 2 * G) {
+        add(acc, k);
+        add(acc2, k + G);
       }
     }
+    for (; k < e; k += G) add(acc, k);
+#pragma unroll
+    for (int j = 0; j < NRHS; ++j) acc[j] += acc2[j];
 #pragma unroll
     for (int j = 0; j < NRHS; ++j) acc[j] = kern::group_sum(acc[j], G);
     if (lane == 0) {

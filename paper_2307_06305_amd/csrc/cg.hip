@@ -119,8 +119,18 @@ __global__ __launch_bounds__(kFinThreads) void finalize(const double* __restrict
                                                         int32_t op, double tol2) {
   __shared__ double w[kFinThreads / 64];
   if ((op == kAlpha || op == kBeta) && sc->done) return;
-  double acc = 0.0;
-  for (int32_t i = threadIdx.x; i < np; i += kFinThreads) acc += partial[i];
+  // eight independent sums per thread keep eight loads in flight; they are
+  // combined in a fixed order, so the result does not depend on timing
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int32_t i = threadIdx.x;
+  for (; i + 7 * kFinThreads < np; i += 8 * kFinThreads) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += partial[i + u * kFinThreads];
+  }
+#pragma unroll
+  for (int u = 0; u < 7; ++u)
+    if (i + u * kFinThreads < np) a[u] += partial[i + u * kFinThreads];
+  double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = acc;
   __syncthreads();

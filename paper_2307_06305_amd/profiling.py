@@ -121,9 +121,46 @@ def read_traffic(path, label="da"):
     return s["kernels"][label]["hbm_bytes"]
 
 
+def kernel_stats(stats_csv, needles=None):
+    """(name, calls, avg us, min us, max us, share %) from a rocprofv3
+    --stats kernel table, largest total time first; needles (substrings)
+    keep only the kernels that match one of them."""
+    rows = []
+    with open(stats_csv) as f:
+        for r in csv.DictReader(f):
+            name = r["Name"].replace("void ", "").split("(")[0]
+            if needles and not any(n in name for n in needles):
+                continue
+            rows.append((name, int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                         float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+                         float(r["Percentage"]), float(r["TotalDurationNs"])))
+    rows.sort(key=lambda t: -t[6])
+    return [t[:6] for t in rows]
+
+
+def write_trace_summary(stats_csv, path, title, command, notes, needles=None, top=24):
+    lines = [f"# {title}", "", "Command (run from the repository root on one MI355X; `cd /tmp` "
+             "first):", "", "```", command, "```", ""]
+    lines += [notes, "", "| kernel | calls | avg us | min us | max us | share % |",
+              "|---|---:|---:|---:|---:|---:|"]
+    for name, calls, avg, mn, mx, pct in kernel_stats(stats_csv, needles)[:top]:
+        lines.append(f"| `{name}` | {calls} | {avg:.1f} | {mn:.1f} | {mx:.1f} | {pct:.2f} |")
+    lines.append("")
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_2307_06305_amd.profiling")
     sub = ap.add_subparsers(dest="cmd", required=True)
+    tr = sub.add_parser("trace", help="summarise a rocprofv3 --stats kernel table")
+    tr.add_argument("--stats", required=True)
+    tr.add_argument("--out", required=True)
+    tr.add_argument("--title", required=True)
+    tr.add_argument("--command", required=True)
+    tr.add_argument("--notes", default="")
+    tr.add_argument("--match", nargs="*", default=None)
+    tr.add_argument("--top", type=int, default=24)
     s = sub.add_parser("summarize")
     s.add_argument("--fetch", required=True)
     s.add_argument("--write", required=True)
@@ -131,6 +168,9 @@ def main(argv=None):
     s.add_argument("--out", required=True)
     s.add_argument("--command", default="")
     a = ap.parse_args(argv)
+    if a.cmd == "trace":
+        write_trace_summary(a.stats, a.out, a.title, a.command, a.notes, a.match, a.top)
+        return 0
     summary = summarize(a.fetch, a.write, a.copy_bytes)
     write_summary(summary, a.out, a.command)
     print(json.dumps(summary["kernels"]), flush=True)

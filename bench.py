@@ -58,6 +58,57 @@ def epochs(fn, reps, n_epochs=5):
     return min(time_launches(fn, reps) for _ in range(n_epochs))
 
 
+def cpu_native(A, e, x, budget_s=3.0):
+    """The native CPU baseline (C++ with OpenMP, rows split statically, four
+    partial sums per row): DA-CSR and CSR SpMV on all host cores the process
+    may use and on one thread, minimum over epochs of the mean time; the DA
+    uplift beside the paper's CPU figures."""
+    import numpy as np
+
+    from paper_2307_06305_amd import cpu
+
+    ncores = len(os.sched_getaffinity(0))
+    da = cpu.arrays(e["rowptr"], e["off"], e["vals"], x, np.int16)
+    cs = cpu.arrays(A.rowptr, A.colids, A.vals, x, np.int32)
+    y = np.empty(A.nrows)
+    T_da = model_bytes(A.nrows, A.ncols, A.nnz, 2)
+    T_csr = model_bytes(A.nrows, A.ncols, A.nnz, 4)
+    out = {"cores": ncores, "cpu": _cpu_model(), "kind": "native C++ OpenMP"}
+    for threads in sorted({ncores, 1}, reverse=True):
+        row = {}
+        for name, fn, arrs, T in (("da", cpu.spmv_da, da, T_da), ("csr", cpu.spmv_csr, cs, T_csr)):
+            fn(A.nrows, arrs[0], arrs[1], arrs[2], arrs[3], y, threads)  # warm
+            t0 = time.perf_counter()
+            fn(A.nrows, arrs[0], arrs[1], arrs[2], arrs[3], y, threads)
+            once = time.perf_counter() - t0
+            reps = max(1, int(budget_s / 5 / max(once, 1e-6)))
+            best = None
+            for _ in range(5):
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    fn(A.nrows, arrs[0], arrs[1], arrs[2], arrs[3], y, threads)
+                dt = (time.perf_counter() - t0) / reps
+                best = dt if best is None else min(best, dt)
+            row[name] = {"ms": round(best * 1e3, 3), "gbs": round(T / best / 1e9, 2)}
+        row["uplift"] = round(row["csr"]["ms"] / row["da"]["ms"] - 1.0, 4)
+        out[f"threads_{threads}"] = row
+        log(f"cpu native, {threads} threads: {row}")
+    out["predicted_uplift"] = round(T_csr / T_da - 1.0, 4)
+    out["paper_cpu_context"] = {"uplift_st": 0.11, "uplift_mt": 0.175, "predicted": 0.20}
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(A, e, x, budget_s=12.0):
     """The CPU oracle's DA-CSR SpMV on the same matrix, repeated until about
     budget_s seconds have passed (NumPy, one thread)."""
@@ -850,6 +901,7 @@ def main():
         res["selector_training"] = bench_selector_training(D, args)
 
     if not args.no_cpu:
+        res["cpu_native"] = cpu_native(A, e, x)
         t_cpu, reps = cpu_baseline(A, e, x)
         res["cpu_baseline"] = {
             "value": round(T_da / t_cpu / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",

@@ -54,12 +54,30 @@ def _compile(src):
     return obj
 
 
+CPU_SRC = os.path.join(PKG, "cpu", "cpu_spmv.cpp")
+CPU_LIB = os.path.join(PKG, "cpu", "libdamn_cpu.so")
+
+
+def _build_cpu():
+    """The native CPU baseline (OpenMP), a library of its own."""
+    tmp = CPU_LIB + ".tmp"
+    cmd = ["g++", "-O3", "-march=x86-64-v3", "-std=c++17", "-fPIC", "-shared", "-fopenmp",
+           CPU_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, CPU_LIB)
+    return CPU_LIB
+
+
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     srcs = HIP_SOURCES + CPP_SOURCES
     jobs = min(len(srcs), max(1, os.cpu_count() or 1))
     with cf.ThreadPoolExecutor(jobs) as ex:
+        cpu = ex.submit(_build_cpu)
         objs = list(ex.map(_compile, srcs))
+        cpu.result()
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)

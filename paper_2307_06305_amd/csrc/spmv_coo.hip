@@ -6,9 +6,9 @@
 // Three launches on the caller's stream, all deterministic (no atomics):
 //   1. y <- beta*y (zeros when beta == 0): rows without entries are done;
 //   2. chunks of kCooChunk consecutive entries per workgroup: indices and
-//      values into LDS with 16-byte direct-to-LDS loads, the products
-//      val * x[col] in place, the runs of equal rows numbered by a workgroup
-//      prefix sum, then G lanes per run sum it.  A run wholly inside the
+//      values into LDS with 16-byte direct-to-LDS loads, the runs of equal
+//      rows numbered by a workgroup prefix sum, then G lanes per run form
+//      and sum its products val * x[col].  A run wholly inside the
 //      chunk updates y; a run cut by the chunk's start leaves its sum in
 //      head[t], one cut only by its end (its row starts in this chunk)
 //      leaves it in tail[t];
@@ -65,12 +65,8 @@ __global__ __launch_bounds__(256) void coo_chunk(int64_t nnz, const int32_t* __r
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 
-  // 2. products in place; each thread counts the runs starting among its
-  //    kPerThread consecutive entries
-  for (int32_t k = threadIdx.x; k < len; k += 256) {
-    const int64_t c = DA ? int64_t(rows_s[k]) + idx_s[k] : int64_t(idx_s[k]);
-    val_s[k] = val_s[k] * x[c];
-  }
+  // 2. each thread counts the runs starting among its kPerThread
+  //    consecutive entries
   const int32_t first = int32_t(threadIdx.x) * kPerThread;
   int32_t cnt = 0;
 #pragma unroll
@@ -99,16 +95,25 @@ __global__ __launch_bounds__(256) void coo_chunk(int64_t nnz, const int32_t* __r
   if (threadIdx.x == 0) seg_s[nseg] = len;
   __syncthreads();
 
-  // 4. G lanes per run; a run wholly inside the chunk updates y, a run cut
-  //    by an edge leaves its sum for the join
+  // 4. G lanes per run form and sum its products (neighbouring runs, that
+  //    is neighbouring rows, on neighbouring lanes, so the x gathers of one
+  //    instruction stay close); a run wholly inside the chunk updates y, a
+  //    run cut by an edge leaves its sum for the join
   const int gl = threadIdx.x % G;
   for (int32_t q = int32_t(threadIdx.x / G); q < nseg; q += 256 / G) {
     const int32_t sk = seg_s[q], ek = seg_s[q + 1];
-    V acc = V(0);
-    for (int32_t k = sk + gl; k < ek; k += G) acc += val_s[k];
+    const int32_t r = rows_s[sk];
+    const V* xs = DA ? x + r : x;
+    V acc = V(0), acc2 = V(0);
+    int32_t k = sk + gl;
+    for (; k + G < ek; k += 2 * G) {
+      acc += val_s[k] * xs[idx_s[k]];
+      acc2 += val_s[k + G] * xs[idx_s[k + G]];
+    }
+    if (k < ek) acc += val_s[k] * xs[idx_s[k]];
+    acc += acc2;
     if (G > 1) acc = group_sum(acc, G);
     if (gl == 0) {
-      const int32_t r = rows_s[sk];
       const bool cont_prev = sk == 0 && edge[0] == r;
       const bool cont_next = ek == len && edge[1] == r;
       if (cont_prev) {  // only the first run

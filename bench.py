@@ -659,14 +659,34 @@ def bench_batch(D, args):
                 M.spmm(X, Y)
 
     t_sep = epochs(separate, 3, 3)
-    # one persistent launch; each matrix reduces rows with the default lane
-    # count of the stream variant for its mean row length
-    for M in mats:
-        mean = M.nnz / max(M.nrows, 1)
-        g = 1 if mean < 4 else 2
-        while g < 16 and g * 16 < mean:
-            g *= 2
-        M.set_config(D.VAR_STREAM, g, 1, 2048)
+    # one launch; each matrix reduces its rows with the lane count of its
+    # stream configuration: first the default for its mean row length, then
+    # the one the autotuner picked for its own product above
+    t_graph_by = {}
+    for how in ("default_lanes", "tuned_lanes"):
+        if how == "default_lanes":
+            tuned = [M.get_config() for M in mats]
+            for M in mats:
+                mean = M.nnz / max(M.nrows, 1)
+                g = 1 if mean < 4 else 2
+                while g < 16 and g * 16 < mean:
+                    g *= 2
+                M.set_config(D.VAR_STREAM, g, 1, 2048)
+        else:
+            for M, c in zip(mats, tuned):
+                M.set_config(D.VAR_STREAM, c["lanes"], 1, 2048)
+        Bt = D.Batch(mats, Xs, Ys, 1.0, 0.0, workgroups=args.batch_workgroups)
+        t_graph_by[how] = epochs(lambda: Bt.run(use_graph=True), 10, 5)
+        Bt.destroy()
+    log(f"batch graph by lane choice: {t_graph_by}")
+    best_how = min(t_graph_by, key=t_graph_by.get)
+    if best_how == "default_lanes":
+        for M in mats:
+            mean = M.nnz / max(M.nrows, 1)
+            g = 1 if mean < 4 else 2
+            while g < 16 and g * 16 < mean:
+                g *= 2
+            M.set_config(D.VAR_STREAM, g, 1, 2048)
     B = D.Batch(mats, Xs, Ys, 1.0, 0.0, workgroups=args.batch_workgroups)
     info = B.info()
     t_graph = epochs(lambda: B.run(use_graph=True), 10, 5)
@@ -679,6 +699,8 @@ def bench_batch(D, args):
     res = {"matrices": count, "rows": total_rows, "nnz": total_nnz, "tiles": info["ntiles"],
            "workgroups": info["workgroups"], "model_bytes": T,
            "graph_us": round(t_graph * 1e6, 1), "graph_gbs": round(T / t_graph / 1e9, 1),
+           "lanes": best_how,
+           "graph_us_by_lanes": {k: round(v * 1e6, 1) for k, v in t_graph_by.items()},
            "direct_us": round(t_direct * 1e6, 1),
            "persistent_1024_us": round(t_persist * 1e6, 1),
            "separate_us": round(t_sep * 1e6, 1), "separate_gbs": round(T / t_sep / 1e9, 1),

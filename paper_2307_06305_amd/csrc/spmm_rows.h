@@ -1,0 +1,118 @@
+// Row reduction of the SpMM stream kernel:
+// Y[r, :] <- alpha * A[r, :] X + beta * Y[r, :] for the rows of one tile
+// whose entries, indices and row pointers already sit in LDS (Sec. 4's
+// product repeated over NRHS vectors).  X is ncols x NRHS and Y nrows x NRHS,
+// row-major, so the NRHS values of one row are adjacent.
+//
+// Each row gets G consecutive lanes.  The NRHS values of a row are cut into
+// pieces of PW = 2 doubles (PAIRS: 16-byte loads and stores; NRHS even, X
+// and Y 16-byte aligned) or of one double.  When the piece count NP is a
+// power of two, the row's lanes split over pieces first: PL = min(G, NP)
+// lanes take neighbouring pieces of the same entry and G / PL lanes step
+// through the entries.  One gather instruction then reads whole runs of
+// neighbouring X rows (the rows r + off for neighbouring r), instead of one
+// piece of each; a wavefront touches a quarter as many cache lines at
+// NRHS = 8.  Other piece counts keep all pieces in every lane (PL = 1).
+//
+// The batched kernel keeps its own unsplit reduction: it inlines every
+// right-hand-side count into one kernel, and with this reduction the merged
+// kernel needs about 96 VGPRs instead of 60, which costs it more occupancy
+// than the split gains.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "damn_device.h"
+
+namespace damn {
+namespace kern {
+
+typedef double spmm_d2 __attribute__((ext_vector_type(2)));
+
+template <typename I, bool DA, int NRHS, bool PAIRS>
+__device__ __forceinline__ void spmm_tile_rows(int G, int32_t r0, int32_t r1, int32_t a0,
+                                               int32_t ar, const double* __restrict__ val_s,
+                                               const I* __restrict__ idx_s,
+                                               const int32_t* __restrict__ rp_s,
+                                               const double* __restrict__ X,
+                                               double* __restrict__ Y, double alpha, double beta,
+                                               bool read_y) {
+  constexpr int PW = PAIRS ? 2 : 1;
+  constexpr int NP = NRHS / PW;
+  constexpr bool kSplit = (NP & (NP - 1)) == 0;
+  const int PL = kSplit ? (G < NP ? G : NP) : 1;  // lanes over pieces
+  const int npl = NP / PL;                         // pieces per lane
+  const int lane = int(threadIdx.x) % G;
+  const int p = lane % PL;   // first piece of this lane
+  const int EL = G / PL;     // lanes over entries
+  const int g = lane / PL;   // this lane's first entry
+  // two entries in flight when a lane holds at most 4 sums (the second set
+  // in acc2); more would cost occupancy
+  constexpr int T = NRHS < 4 ? NRHS : 4;
+  const bool twin = npl * PW <= T;
+  for (int32_t r = r0 + int32_t(threadIdx.x) / G; r < r1; r += 256 / G) {
+    const int32_t s = rp_s[r - ar] - a0, e = rp_s[r + 1 - ar] - a0;
+    const double* Xs = DA ? X + int64_t(r) * NRHS : X;
+    double acc[NRHS], acc2[T];
+#pragma unroll
+    for (int j = 0; j < NRHS; ++j) acc[j] = 0.0;
+#pragma unroll
+    for (int j = 0; j < T; ++j) acc2[j] = 0.0;
+    auto add = [&](auto& a, int32_t k) {
+      constexpr int N = sizeof(a) / sizeof(double);
+      const double v = val_s[k];
+      const double* xr = Xs + int64_t(idx_s[k]) * NRHS;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        if ((i + 1) * PW <= N && i < npl) {
+          const int q = p + i * PL;
+          if (PAIRS) {
+            const spmm_d2 xv = reinterpret_cast<const spmm_d2*>(xr)[q];
+            a[2 * i] += v * xv.x;
+            a[2 * i + 1] += v * xv.y;
+          } else {
+            a[i] += v * xr[q];
+          }
+        }
+      }
+    };
+    int32_t k = s + g;
+    if (twin) {
+      for (; k + EL < e; k += 2 * EL) {
+        add(acc, k);
+        add(acc2, k + EL);
+      }
+    }
+    for (; k < e; k += EL) add(acc, k);
+#pragma unroll
+    for (int j = 0; j < NRHS; ++j) {
+      if (j < npl * PW) {
+        if (j < T) acc[j] += acc2[j];
+        // sum over the lanes of this row that hold the same pieces
+        for (int o = G >> 1; o >= PL; o >>= 1) acc[j] += __shfl_xor(acc[j], o, G);
+      }
+    }
+    if (g == 0) {
+      double* yr = Y + int64_t(r) * NRHS;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        if (i < npl) {
+          const int q = p + i * PL;
+          if (PAIRS) {
+            spmm_d2 out;
+            out.x = finish(acc[2 * i], alpha, beta, read_y, yr + 2 * q);
+            out.y = finish(acc[2 * i + 1], alpha, beta, read_y, yr + 2 * q + 1);
+            reinterpret_cast<spmm_d2*>(yr)[q] = out;
+          } else {
+            yr[q] = finish(acc[i], alpha, beta, read_y, yr + q);
+          }
+        }
+      }
+    }
+  }
+}
+
+}  // namespace kern
+}  // namespace damn

@@ -1,23 +1,22 @@
 // SpMM Y <- alpha*A*X + beta*Y, stream variant: the tiles of the SpMV stream
 // kernel (indices, float64 values and row pointers copied into LDS with
 // 16-byte direct-to-LDS loads, the entries non-temporal), then G lanes per
-// row accumulate all NRHS right-hand sides at once.  X is ncols x NRHS and
-// Y nrows x NRHS, row-major (the NRHS values of a row adjacent); with PAIRS
-// (NRHS even, X and Y 16-byte aligned) they move as 16-byte pairs.  Each
-// index and value is read once for all right-hand sides (Sec. 4's product
-// repeated over nrhs vectors).
+// row, split over the right-hand sides and the entries, accumulate all NRHS
+// right-hand sides at once.  X is ncols x NRHS and Y nrows x NRHS, row-major
+// (the NRHS values of a row adjacent); with PAIRS (NRHS even, X and Y 16-byte
+// aligned) they move as 16-byte pairs.  Each index and value is read once
+// for all right-hand sides (Sec. 4's product repeated over nrhs vectors).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
 #include "damn_device.h"
 #include "damn_kernels.h"
+#include "spmm_rows.h"
 #include "spmv_templates.h"
 
 namespace damn {
 namespace kern {
-
-typedef double d2 __attribute__((ext_vector_type(2)));
 
 template <typename I, bool DA, int G, int NRHS, bool PAIRS>
 __global__ __launch_bounds__(256) void spmm_stream(
@@ -72,61 +71,9 @@ __global__ __launch_bounds__(256) void spmm_stream(
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 
-  // 2. G lanes per row, NRHS sums each
-  const int lane = threadIdx.x % G;
-  for (int32_t r = r0 + int32_t(threadIdx.x / G); r < r1; r += 256 / G) {
-    const int32_t s = rp_s[r - ar] - a0, e = rp_s[r + 1 - ar] - a0;
-    const double* Xs = DA ? X + int64_t(r) * NRHS : X;
-    // up to 4 right-hand sides, two entries in flight per lane (partial sums
-    // acc for even steps, acc2 for odd ones); more would spill registers
-    double acc[NRHS], acc2[NRHS];
-#pragma unroll
-    for (int j = 0; j < NRHS; ++j) acc[j] = acc2[j] = 0.0;
-    auto add = [&](double* a, int32_t k) {
-      const double v = val_s[k];
-      const double* xr = Xs + int64_t(idx_s[k]) * NRHS;
-      if (PAIRS) {
-#pragma unroll
-        for (int j = 0; j < NRHS / 2; ++j) {
-          const d2 xv = reinterpret_cast<const d2*>(xr)[j];
-          a[2 * j] += v * xv.x;
-          a[2 * j + 1] += v * xv.y;
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < NRHS; ++j) a[j] += v * xr[j];
-      }
-    };
-    int32_t k = s + lane;
-    if (NRHS <= 4) {
-      for (; k + G < e; k += 2 * G) {
-        add(acc, k);
-        add(acc2, k + G);
-      }
-    }
-    for (; k < e; k += G) add(acc, k);
-#pragma unroll
-    for (int j = 0; j < NRHS; ++j) acc[j] += acc2[j];
-    if (G > 1) {
-#pragma unroll
-      for (int j = 0; j < NRHS; ++j) acc[j] = group_sum(acc[j], G);
-    }
-    if (lane == 0) {
-      double* yr = Y + int64_t(r) * NRHS;
-      if (PAIRS) {
-#pragma unroll
-        for (int j = 0; j < NRHS / 2; ++j) {
-          d2 out;
-          out.x = finish(acc[2 * j], alpha, beta, read_y != 0, yr + 2 * j);
-          out.y = finish(acc[2 * j + 1], alpha, beta, read_y != 0, yr + 2 * j + 1);
-          reinterpret_cast<d2*>(yr)[j] = out;
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < NRHS; ++j) yr[j] = finish(acc[j], alpha, beta, read_y != 0, yr + j);
-      }
-    }
-  }
+  // 2. G lanes per row, split over the right-hand sides and the entries
+  spmm_tile_rows<I, DA, NRHS, PAIRS>(G, r0, r1, a0, ar, val_s, idx_s, rp_s, X, Y, alpha, beta,
+                                     read_y != 0);
 }
 
 }  // namespace kern

@@ -5,11 +5,14 @@
 // device memory; each iteration is five launches:
 //   q = A p  with the p.q partial sums        (stream SpMV, dot epilogue)
 //   alpha = rho / p.q                         (one workgroup)
-//   x += alpha p, r -= alpha q, r.r partials  (one pass over the vectors)
+//   r -= alpha q, r.r partials                (one pass over r and q)
 //   beta, stop test                           (one workgroup)
-//   p = r + beta p
-// Once the stop test fires, a device flag makes every later launch return at
-// once, so the host only reads the flag every `check_every` iterations.
+//   x += alpha p, p = r + beta p              (one pass over x, p and r)
+// The x update waits for the pass that reads p anyway, which saves a read
+// and a write of p per iteration against updating x beside r.  Once the stop
+// test fires, a device flag makes every later launch return at once (the
+// iteration's own x update still runs), so the host only reads the flag
+// every `check_every` iterations.
 // Dot products are summed in float64 in a fixed order (per-workgroup
 // partials, then one workgroup), so results do not depend on scheduling.
 #include <hip/hip_runtime.h>
@@ -31,7 +34,9 @@ struct Scal {
   double beta;
   double stop2;   // stop when rho <= stop2
   double b2;      // squared norm of the right-hand side of this solve
-  int32_t done, converged, breakdown, iters, max_iter, zero, pad0, pad1;
+  int32_t done, converged, breakdown, iters, max_iter, zero;
+  int32_t last;  // the stop test fired this iteration: its x update is still due
+  int32_t pad;
 };
 
 constexpr int kVecBlocks = 1024;  // workgroups of the vector kernels
@@ -118,7 +123,11 @@ __global__ __launch_bounds__(kFinThreads) void finalize(const double* __restrict
                                                         int32_t np, Scal* __restrict__ sc,
                                                         int32_t op, double tol2) {
   __shared__ double w[kFinThreads / 64];
-  if ((op == kAlpha || op == kBeta) && sc->done) return;
+  if ((op == kAlpha || op == kBeta) && sc->done) {
+    // the first skipped alpha step follows the final x update
+    if (op == kAlpha && threadIdx.x == 0) sc->last = 0;
+    return;
+  }
   // eight independent sums per thread keep eight loads in flight; they are
   // combined in a fixed order, so the result does not depend on timing
   double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -161,9 +170,11 @@ __global__ __launch_bounds__(kFinThreads) void finalize(const double* __restrict
         sc->rho = s;
         sc->converged = 1;
         sc->done = 1;
+        sc->last = 1;
       } else if (sc->iters >= sc->max_iter) {
         sc->rho = s;
         sc->done = 1;
+        sc->last = 1;
       } else {
         sc->beta = s / sc->rho;
         sc->rho = s;
@@ -175,14 +186,13 @@ __global__ __launch_bounds__(kFinThreads) void finalize(const double* __restrict
   }
 }
 
-// x += alpha p; r -= alpha q; partial[block] = sum r^2.  V = double or float
-// (float: the update is formed in float64 and rounded once).
+// r -= alpha q; partial[block] = sum r^2.  V = double or float (float: the
+// update is formed in float64 and rounded once).
 template <typename V>
-__global__ __launch_bounds__(256) void update_xr(int64_t n, V* __restrict__ x, V* __restrict__ r,
-                                                 const V* __restrict__ p,
-                                                 const V* __restrict__ q,
-                                                 const Scal* __restrict__ sc,
-                                                 double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void update_r(int64_t n, V* __restrict__ r,
+                                                const V* __restrict__ q,
+                                                const Scal* __restrict__ sc,
+                                                double* __restrict__ partial) {
   if (sc->done) return;
   const double a = sc->alpha;
   int64_t s, e;
@@ -190,18 +200,15 @@ __global__ __launch_bounds__(256) void update_xr(int64_t n, V* __restrict__ x, V
   double acc = 0.0;
   typedef Pack<V> P;
   for_packs<V>(s, e, [&](int64_t base) {
-      typename P::vec xv = P::load(x + base), rv = P::load(r + base);
-      const typename P::vec pv = P::load(p + base), qv = P::load(q + base);
+      typename P::vec rv = P::load(r + base);
+      const typename P::vec qv = P::load(q + base);
 #pragma unroll
       for (int k = 0; k < P::kN; ++k) {
-        xv[k] = V(double(xv[k]) + a * double(pv[k]));
         rv[k] = V(double(rv[k]) - a * double(qv[k]));
         acc += double(rv[k]) * double(rv[k]);
       }
-      P::store(x + base, xv);
       P::store(r + base, rv);
     }, [&](int64_t i) {
-      x[i] = V(double(x[i]) + a * double(p[i]));
       const V rn = V(double(r[i]) - a * double(q[i]));
       r[i] = rn;
       acc += double(rn) * double(rn);
@@ -210,23 +217,32 @@ __global__ __launch_bounds__(256) void update_xr(int64_t n, V* __restrict__ x, V
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
-// p = r + beta p
+// x += alpha p, then p = r + beta p (p only while the iteration goes on)
 template <typename V>
-__global__ __launch_bounds__(256) void update_p(int64_t n, V* __restrict__ p,
-                                                const V* __restrict__ r,
-                                                const Scal* __restrict__ sc) {
-  if (sc->done) return;
-  const double bt = sc->beta;
+__global__ __launch_bounds__(256) void update_xp(int64_t n, V* __restrict__ x, V* __restrict__ p,
+                                                 const V* __restrict__ r,
+                                                 const Scal* __restrict__ sc) {
+  if (sc->done && !sc->last) return;
+  const bool more = !sc->done;
+  const double a = sc->alpha, bt = sc->beta;
   int64_t s, e;
   slice(n, 1024, &s, &e);
   typedef Pack<V> P;
   for_packs<V>(s, e, [&](int64_t base) {
-      typename P::vec pv = P::load(p + base);
-      const typename P::vec rv = P::load(r + base);
+      typename P::vec xv = P::load(x + base), pv = P::load(p + base);
 #pragma unroll
-      for (int k = 0; k < P::kN; ++k) pv[k] = V(double(rv[k]) + bt * double(pv[k]));
-      P::store(p + base, pv);
-    }, [&](int64_t i) { p[i] = V(double(r[i]) + bt * double(p[i])); });
+      for (int k = 0; k < P::kN; ++k) xv[k] = V(double(xv[k]) + a * double(pv[k]));
+      P::store(x + base, xv);
+      if (more) {
+        const typename P::vec rv = P::load(r + base);
+#pragma unroll
+        for (int k = 0; k < P::kN; ++k) pv[k] = V(double(rv[k]) + bt * double(pv[k]));
+        P::store(p + base, pv);
+      }
+    }, [&](int64_t i) {
+      x[i] = V(double(x[i]) + a * double(p[i]));
+      if (more) p[i] = V(double(r[i]) + bt * double(p[i]));
+    });
 }
 
 // Inner solve start: rh = float(r / ||r||), d = 0, p = rh; partial = sum rh^2
@@ -381,12 +397,12 @@ int iterate(damn_mat M, damn_cg_work* w, V* xs, V* rs, V* ps, V* qs, int check_e
       DAMN_HIP_TRY(launch_spmv_dot(a, lanes, ps, w->partial, &w->sc[0].done));
       hipLaunchKernelGGL(cgk::finalize, dim3(1), dim3(cgk::kFinThreads), 0, s, w->partial,
                          int32_t(M->ntiles), w->sc, int32_t(cgk::kAlpha), 0.0);
-      hipLaunchKernelGGL(cgk::update_xr<V>, dim3(cgk::kVecBlocks), dim3(256), 0, s, n, xs, rs,
-                         ps, qs, w->sc, w->partial);
+      hipLaunchKernelGGL(cgk::update_r<V>, dim3(cgk::kVecBlocks), dim3(256), 0, s, n, rs, qs,
+                         w->sc, w->partial);
       hipLaunchKernelGGL(cgk::finalize, dim3(1), dim3(cgk::kFinThreads), 0, s, w->partial,
                          int32_t(cgk::kVecBlocks), w->sc, int32_t(cgk::kBeta), 0.0);
-      hipLaunchKernelGGL(cgk::update_p<V>, dim3(cgk::kVecBlocks), dim3(256), 0, s, n, ps, rs,
-                         w->sc);
+      hipLaunchKernelGGL(cgk::update_xp<V>, dim3(cgk::kVecBlocks), dim3(256), 0, s, n, xs, ps,
+                         rs, w->sc);
     }
     DAMN_HIP_TRY(hipGetLastError());
     const int st = read_scal(w, s);

@@ -97,8 +97,18 @@ def test_cg_iteration_limit_and_zero_rhs():
     A = laplace_2d_5pt(30)
     A64, A32 = _handles(A, "da")
     b = uniform_vector(A.nrows, 3)
-    info = D.cg(A64, dev(b), dev(np.zeros(A.nrows)), max_iter=5, check_every=2)
-    assert not info["converged"] and info["iters"] == 5
+    for max_iter, every in ((5, 2), (4, 4), (6, 1)):
+        xd = dev(np.zeros(A.nrows))
+        info = D.cg(A64, dev(b), xd, max_iter=max_iter, check_every=every)
+        assert not info["converged"] and info["iters"] == max_iter
+        # the stopped iterate carries its last x update: it matches the
+        # oracle's CG after the same number of steps
+        ref = OC.cg_fp64(
+            lambda v: OS.spmv_csr(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, v), b,
+            max_iter=max_iter)
+        assert ref["iters"] == max_iter
+        np.testing.assert_allclose(host(xd), ref["x"], rtol=0, atol=1e-12 * np.abs(ref["x"]).max())
+        assert abs(info["rel_res"] - ref["true_rel_res"]) <= 1e-12
     info = D.cg(A64, dev(np.zeros(A.nrows)), dev(np.ones(A.nrows)))
     assert info["converged"] and info["iters"] == 0
     A64.destroy()

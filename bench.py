@@ -759,7 +759,11 @@ def main():
     ap.add_argument("--batch-workgroups", type=int, default=0)
     ap.add_argument("--profile", action="store_true",
                     help="short run for counter collection: copy probe, then DA and CSR SpMV "
-                         "with the default stream configuration")
+                         "with the launch shapes of --profile-da and --profile-csr")
+    ap.add_argument("--profile-da", default="stream_g2_t4096",
+                    help="DA-CSR launch shape of the counter run")
+    ap.add_argument("--profile-csr", default="stream_g2_t2048",
+                    help="CSR launch shape of the counter run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
@@ -801,14 +805,19 @@ def main():
         for _ in range(3):
             D.stream_copy(src, dst)
         del src, dst
-        M.set_config(D.VAR_STREAM, 2, 1, 2048)
-        Cm.set_config(D.VAR_STREAM, 2, 1, 2048)
+        from paper_2307_06305_amd.profiling import stream_launch
+
+        g, t = stream_launch(args.profile_da)
+        M.set_config(D.VAR_STREAM, g, 1, t)
+        g, t = stream_launch(args.profile_csr)
+        Cm.set_config(D.VAR_STREAM, g, 1, t)
         for _ in range(10):
             M.spmv(xd, yd)
         for _ in range(10):
             Cm.csr_spmv(xd, yc)
         torch.cuda.synchronize()
-        print(json.dumps({"profile": "done", "copy_bytes": 1 << 30}), flush=True)
+        print(json.dumps({"profile": "done", "copy_bytes": 1 << 30, "da": args.profile_da,
+                          "csr": args.profile_csr}), flush=True)
         return
 
     # streaming ceiling: a plain 16-byte-load read of 2 GiB
@@ -863,10 +872,9 @@ def main():
     # sources are unchanged and the timed launch shape is the profiled one
     from paper_2307_06305_amd.profiling import read_traffic
 
-    traffic = None
-    if config_name(best_da) == "stream_g2_t2048":
-        tb = read_traffic(os.path.join(ROOT, "profiles", "spmv_27pt128_traffic.md"))
-        traffic = None if tb is None else int(round(tb))
+    tb = read_traffic(os.path.join(ROOT, "profiles", "spmv_27pt128_traffic.md"), "da",
+                      launch=config_name(best_da))
+    traffic = None if tb is None else int(round(tb))
     res = {
         "metric": "DA-CSR vs CSR SpMV effective GB/s, % HBM peak, speedup; CG time to 1e-10",
         "value": round(T_da / (ms_per_step * 1e-3) / 1e9, 1),

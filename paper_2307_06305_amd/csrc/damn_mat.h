@@ -25,7 +25,8 @@ struct damn_mat_s {
   damn_config cfg{};
   int32_t* d_tiles = nullptr;  // stream tiles: first row of each tile, plus nrows
   int64_t ntiles = 0;
-  int32_t tiles_cap = 0;
+  int32_t tiles_req = 0;  // entry cap the tiles were built for
+  int32_t tiles_cap = 0;  // largest entry count of a tile that is not one long row
   damn_cg_work* cg = nullptr;
 };
 

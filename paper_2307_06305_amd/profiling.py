@@ -27,9 +27,25 @@ import re
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/spmv_kernels.hip", "csrc/spmv_templates.h", "csrc/damn_device.h")
-DA_KERNEL = "spmv_stream<short, double, true, 2, false, double>"
-CSR_KERNEL = "spmv_stream<int, double, false, 2, false, double>"
+# the product kernels and the host code that cuts their tiles
+KERNEL_SOURCES = ("csrc/spmv_kernels.hip", "csrc/spmv_templates.h", "csrc/damn_device.h",
+                  "csrc/api.hip")
+DA_LAUNCH = "stream_g2_t4096"   # launch shapes the counter runs use by default
+CSR_LAUNCH = "stream_g2_t2048"
+
+
+def stream_launch(name):
+    """(lanes, tile) of a stream launch name such as stream_g2_t4096."""
+    m = re.fullmatch(r"stream_g(\d+)_t(\d+)", name)
+    if not m:
+        raise ValueError(f"not a stream launch name: {name!r}")
+    return int(m.group(1)), int(m.group(2))
+
+
+def kernel_name(label, launch):
+    g, _ = stream_launch(launch)
+    index = "short" if label == "da" else "int"
+    return f"spmv_stream<{index}, double, {'true' if label == 'da' else 'false'}, {g}, false, double>"
 COPY_KERNEL = "stream_copy"
 
 
@@ -61,18 +77,20 @@ def _find(table, needle):
     raise KeyError(f"no kernel matching {needle!r}")
 
 
-def summarize(fetch_csv, write_csv, copy_bytes):
+def summarize(fetch_csv, write_csv, copy_bytes, launch_da=DA_LAUNCH, launch_csr=CSR_LAUNCH):
     fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
     write = _per_kernel(write_csv, "WRITE_SIZE")
     cf = _find(fetch, COPY_KERNEL)[0] * 1024 / copy_bytes
     cw = _find(write, COPY_KERNEL)[0] * 1024 / copy_bytes
     out = {"copy_bytes": copy_bytes, "fetch_scale": cf, "write_scale": cw,
            "source_sha256": kernel_source_hash(), "kernels": {}}
-    for label, needle in (("da", DA_KERNEL), ("csr", CSR_KERNEL)):
+    for label, launch in (("da", launch_da), ("csr", launch_csr)):
+        needle = kernel_name(label, launch)
         fk, nf = _find(fetch, needle)
         wk, nw = _find(write, needle)
         out["kernels"][label] = {
-            "kernel": needle, "dispatches": [nf, nw], "fetch_kib": fk, "write_kib": wk,
+            "kernel": needle, "launch": launch, "dispatches": [nf, nw], "fetch_kib": fk,
+            "write_kib": wk,
             "hbm_read_bytes": fk * 1024 / cf, "hbm_write_bytes": wk * 1024 / cw,
             "hbm_bytes": fk * 1024 / cf + wk * 1024 / cw}
     return out
@@ -97,7 +115,7 @@ def write_summary(summary, path, command):
         "|---|---:|---:|---:|---:|---:|",
     ]
     for k in (da, csr):
-        lines.append(f"| `{k['kernel']}` | {k['fetch_kib']:.0f} | {k['write_kib']:.0f} | "
+        lines.append(f"| `{k['kernel']}` ({k['launch']}) | {k['fetch_kib']:.0f} | {k['write_kib']:.0f} | "
                      f"{k['hbm_read_bytes']:.4g} | {k['hbm_write_bytes']:.4g} | "
                      f"{k['hbm_bytes']:.4g} |")
     lines += ["", "Traffic model (Eq. 3 plus x once and y written): DA 599,372,724 B, "
@@ -106,9 +124,10 @@ def write_summary(summary, path, command):
         f.write("\n".join(lines))
 
 
-def read_traffic(path, label="da"):
+def read_traffic(path, label="da", launch=None):
     """HBM bytes per launch recorded in a summary, or None if the summary is
-    missing or the kernel sources changed since it was taken."""
+    missing, the kernel sources changed since it was taken, or it recorded
+    another launch shape than `launch`."""
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -118,7 +137,10 @@ def read_traffic(path, label="da"):
     s = json.loads(m.group(1))
     if s.get("source_sha256") != kernel_source_hash():
         return None
-    return s["kernels"][label]["hbm_bytes"]
+    k = s["kernels"][label]
+    if launch is not None and k.get("launch") != launch:
+        return None
+    return k["hbm_bytes"]
 
 
 def kernel_stats(stats_csv, needles=None):
@@ -167,11 +189,13 @@ def main(argv=None):
     s.add_argument("--copy-bytes", type=int, required=True)
     s.add_argument("--out", required=True)
     s.add_argument("--command", default="")
+    s.add_argument("--launch-da", default=DA_LAUNCH)
+    s.add_argument("--launch-csr", default=CSR_LAUNCH)
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         write_trace_summary(a.stats, a.out, a.title, a.command, a.notes, a.match, a.top)
         return 0
-    summary = summarize(a.fetch, a.write, a.copy_bytes)
+    summary = summarize(a.fetch, a.write, a.copy_bytes, a.launch_da, a.launch_csr)
     write_summary(summary, a.out, a.command)
     print(json.dumps(summary["kernels"]), flush=True)
     return 0

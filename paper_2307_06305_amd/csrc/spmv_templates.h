@@ -173,6 +173,9 @@ __global__ __launch_bounds__(256) void spmv_stream(
   for (int32_t r = r0 + int32_t(threadIdx.x / G); r < r1; r += 256 / G) {
     const int32_t s = rp_s[r - ar] - a0, e = rp_s[r + 1 - ar] - a0;
     const V* xs = DA ? x + r : x;
+    // the dot epilogue's w_r, loaded with the row's gathers rather than
+    // after its sum
+    const V wr = (DOT && w && lane == 0) ? w[r] : V(0);
     V acc[4] = {V(0), V(0), V(0), V(0)};
     int32_t k = s + lane;
     for (; k + 3 * G < e; k += 4 * G) {
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(256) void spmv_stream(
     if (lane == 0) {
       const V yr = finish(sum, alpha, beta, read_y != 0, y + r);
       y[r] = yr;
-      if (DOT) dot += double(yr) * double(w ? w[r] : yr);
+      if (DOT) dot += double(yr) * double(w ? wr : yr);
     }
   }
   if (DOT) {

@@ -332,9 +332,12 @@ int damn_spmm(damn_mat A, const void* X, void* Y, int32_t nrhs, double alpha,
  *                    two; 1 = one row per lane), `unroll` independent partial
  *                    sums per lane (1, 2 or 4).
  *   DAMN_VAR_STREAM: workgroups take tiles of whole rows holding at most
- *                    `tile` entries, stream offsets and values with aligned
+ *                    `tile` entries (and at most 512 rows; a tile that
+ *                    ends before the last row is cut back to a power-of-two
+ *                    row count), stream offsets and values with aligned
  *                    16-byte loads through LDS, and reduce each row with
- *                    `lanes` lanes (1..64).  `unroll` unused.
+ *                    `lanes` lanes (1..64).  A row longer than `tile` is
+ *                    reduced by a whole workgroup.  `unroll` unused.
  */
 typedef enum { DAMN_VAR_VECTOR = 0, DAMN_VAR_STREAM = 1 } damn_variant;
 
@@ -342,7 +345,8 @@ typedef struct {
   int32_t variant;
   int32_t lanes;
   int32_t unroll;
-  int32_t tile; /* stream variant only: entries per tile (256..8192) */
+  int32_t tile; /* stream variant only: entries per tile (256..4096, a
+                   multiple of 8; otherwise DAMN_ERR_UNSUPPORTED) */
 } damn_config;
 
 /* Set / read the configuration used by damn_spmv, damn_csr_spmv and

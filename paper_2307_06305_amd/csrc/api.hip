@@ -28,7 +28,7 @@ namespace damn {
 int build_tiles(damn_mat A, int32_t cap) {
   if (A->d_tiles && A->tiles_req == cap) return DAMN_OK;
   std::vector<int32_t> starts;
-  int32_t largest = 0;
+  int32_t largest = 0, most_rows = 1;
   try {
     // rows of the stored structure: block rows for block formats
     const int32_t nr = int32_t(A->h_rowptr.size()) - 1;
@@ -49,6 +49,7 @@ int build_tiles(damn_mat A, int32_t cap) {
         r = first + m;
       }
       largest = std::max(largest, rp[r] - rp[first]);
+      most_rows = std::max(most_rows, r - first);
     }
     starts.push_back(nr);
   } catch (const std::bad_alloc&) {
@@ -66,6 +67,7 @@ int build_tiles(damn_mat A, int32_t cap) {
   A->ntiles = int64_t(starts.size()) - 1;
   A->tiles_req = cap;
   A->tiles_cap = largest;
+  A->tiles_rows = most_rows;
   return DAMN_OK;
 }
 
@@ -241,6 +243,7 @@ int run_spmv(damn_mat A, const void* x, void* y, double alpha, double beta, void
     a.tile_row = A->d_tiles;
     a.ntiles = A->ntiles;
     a.cap = A->tiles_cap;
+    a.tile_rows = A->tiles_rows;
     const hipError_t e = launch_spmv_bsr(a, A->cfg.lanes > 16 ? 16 : A->cfg.lanes);
     return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
   }
@@ -250,6 +253,7 @@ int run_spmv(damn_mat A, const void* x, void* y, double alpha, double beta, void
     a.tile_row = A->d_tiles;
     a.ntiles = A->ntiles;
     a.cap = A->tiles_cap;
+    a.tile_rows = A->tiles_rows;
   }
   const hipError_t e = launch_spmv(a, A->cfg.variant, A->cfg.lanes, A->cfg.unroll);
   return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
@@ -513,6 +517,7 @@ int damn_spmm(damn_mat A, const void* X, void* Y, int32_t nrhs, double alpha, do
     a.tile_row = A->d_tiles;
     a.ntiles = A->ntiles;
     a.cap = A->tiles_cap;
+    a.tile_rows = A->tiles_rows;
     const hipError_t e = launch_spmm_stream(a, A->cfg.lanes, nrhs);
     return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
   }

@@ -358,6 +358,7 @@ SpmvArgs stream_args(damn_mat A, const void* x, void* y, double alpha, double be
   a.tile_row = A->d_tiles;
   a.ntiles = A->ntiles;
   a.cap = A->tiles_cap;
+  a.tile_rows = A->tiles_rows;
   a.stream = s;
   return a;
 }

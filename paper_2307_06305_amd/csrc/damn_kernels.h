@@ -52,6 +52,7 @@ struct SpmvArgs {
   const int32_t* tile_row = nullptr;
   int64_t ntiles = 0;
   int32_t cap = 0;
+  int32_t tile_rows = kMaxTileRows;  // most rows (block rows) of any tile
   hipStream_t stream = nullptr;
 };
 

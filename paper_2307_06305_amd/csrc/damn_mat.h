@@ -27,6 +27,7 @@ struct damn_mat_s {
   int64_t ntiles = 0;
   int32_t tiles_req = 0;  // entry cap the tiles were built for
   int32_t tiles_cap = 0;  // largest entry count of a tile that is not one long row
+  int32_t tiles_rows = 0;  // most rows of any tile
   damn_cg_work* cg = nullptr;
 };
 

@@ -83,7 +83,7 @@ namespace {
 template <typename I, bool DA, int G, int NRHS, bool PAIRS>
 hipError_t go(const SpmvArgs& a) {
   hipLaunchKernelGGL((kern::spmm_stream<I, DA, G, NRHS, PAIRS>), dim3(uint32_t(a.ntiles)),
-                     dim3(256), (kern::TileLds<I, double>::bytes(a.cap)), a.stream, a.tile_row,
+                     dim3(256), (kern::TileLds<I, double>::bytes(a.cap, a.tile_rows)), a.stream, a.tile_row,
                      a.rowptr, static_cast<const I*>(a.idx), static_cast<const double*>(a.val),
                      static_cast<const double*>(a.x), static_cast<double*>(a.y), a.alpha, a.beta,
                      a.read_y, a.cap);

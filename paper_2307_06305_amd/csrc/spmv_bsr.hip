@@ -33,9 +33,9 @@ struct BsrLds {
   __host__ __device__ static constexpr int32_t val_slots(int32_t cap) {
     return ((cap + kAlign) * B * B + 16 + 15) & ~15;
   }
-  static constexpr size_t bytes(int32_t cap) {
+  static constexpr size_t bytes(int32_t cap, int32_t rows) {
     return size_t(val_slots(cap)) * sizeof(S) + size_t(idx_slots(cap)) * sizeof(I) +
-           sizeof(int32_t) * (kMaxTileRows + 16);
+           sizeof(int32_t) * (size_t(rows) + 16);
   }
 };
 
@@ -137,7 +137,7 @@ template <typename I, typename S, typename V, bool DA, int B, int G>
 hipError_t bsr_g(const SpmvArgs& a) {
   if (a.ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL((kern::spmv_bsr_stream<I, S, V, DA, B, G>), dim3(uint32_t(a.ntiles)),
-                     dim3(256), (kern::BsrLds<I, S, B>::bytes(a.cap)), a.stream, a.tile_row,
+                     dim3(256), (kern::BsrLds<I, S, B>::bytes(a.cap, a.tile_rows)), a.stream, a.tile_row,
                      a.rowptr, static_cast<const I*>(a.idx), static_cast<const S*>(a.val),
                      static_cast<const V*>(a.x), static_cast<V*>(a.y), V(a.alpha), V(a.beta),
                      a.read_y, a.cap);

@@ -88,18 +88,24 @@ __global__ __launch_bounds__(256) void spmv_vector(
 // ---------------------------------------------------------------------------
 
 // LDS layout of one tile: indices and values of up to `cap` entries plus the
-// alignment slack, then the row pointers.
+// alignment slack, then the row pointers of up to `rows` rows (the host's
+// largest tile), so short-row tiles leave LDS for more workgroups per CU.
 template <typename I, typename S>
 struct TileLds {
   // the copied range starts at the tile's first entry rounded down to kAlign
   // entries, so 16-byte pieces of both arrays start on 16-byte boundaries
   static constexpr int32_t kAlign =
       int32_t(16 / sizeof(I) > 16 / sizeof(S) ? 16 / sizeof(I) : 16 / sizeof(S));
-  // entries per array: cap + (kAlign - 1) slack + up to one partial piece
-  // (at most cap + 30), rounded to 16 so every array starts 16-byte aligned
-  __host__ __device__ static constexpr int32_t slots(int32_t cap) { return (cap + 32 + 15) & ~15; }
-  static constexpr size_t bytes(int32_t cap) {
-    return size_t(slots(cap)) * (sizeof(I) + sizeof(S)) + sizeof(int32_t) * (kMaxTileRows + 16);
+  // entries per array: cap + (kAlign - 1) leading slack + at most
+  // kAlign - 1 entries of the last partial piece, rounded to 16 so every
+  // array starts 16-byte aligned
+  __host__ __device__ static constexpr int32_t slots(int32_t cap) {
+    return (cap + 2 * kAlign - 2 + 15) & ~15;
+  }
+  // the row-pointer copy covers rows + 1 entries from a start rounded down
+  // to 4, in pieces of 4: at most rows + 8 entries
+  static constexpr size_t bytes(int32_t cap, int32_t rows) {
+    return size_t(slots(cap)) * (sizeof(I) + sizeof(S)) + sizeof(int32_t) * (size_t(rows) + 16);
   }
 };
 
@@ -155,8 +161,9 @@ __global__ __launch_bounds__(256) void spmv_stream(
 
   // 1. entries [a0, p1) into LDS (a0 = p0 rounded down to kAlign; the copies
   //    stay within slots entries), and the row pointers rowptr[ar .. r1]
-  //    (ar = r0 rounded down to 4; at most kMaxTileRows + 4 entries, from an
-  //    allocation padded for the last piece)
+  //    (ar = r0 rounded down to 4; at most rows + 4 entries for a tile of
+  //    `rows` rows, rounded up to a whole piece: within the rows + 16 the
+  //    launch allocates for its largest tile)
   const int32_t a0 = p0 & ~(L::kAlign - 1);
   copy_to_lds(val_s, val, a0, p1 - a0);
   copy_to_lds(idx_s, idx, a0, p1 - a0);
@@ -252,7 +259,7 @@ template <typename I, typename S, typename V, bool DA, int G>
 hipError_t stream_g(const SpmvArgs& a) {
   if (a.ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, false, S>), dim3(uint32_t(a.ntiles)),
-                     dim3(256), (kern::TileLds<I, S>::bytes(a.cap)), a.stream, a.tile_row,
+                     dim3(256), (kern::TileLds<I, S>::bytes(a.cap, a.tile_rows)), a.stream, a.tile_row,
                      a.rowptr, static_cast<const I*>(a.idx), static_cast<const S*>(a.val),
                      static_cast<const V*>(a.x), static_cast<V*>(a.y), V(a.alpha), V(a.beta),
                      a.read_y, a.cap, nullptr, nullptr, nullptr);
@@ -276,7 +283,7 @@ template <typename I, typename V, bool DA, int G>
 hipError_t stream_dot_g(const SpmvArgs& a, const void* w, double* partial, const int32_t* done) {
   if (a.ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, true, V>), dim3(uint32_t(a.ntiles)),
-                     dim3(256), (kern::TileLds<I, V>::bytes(a.cap)), a.stream, a.tile_row,
+                     dim3(256), (kern::TileLds<I, V>::bytes(a.cap, a.tile_rows)), a.stream, a.tile_row,
                      a.rowptr, static_cast<const I*>(a.idx), static_cast<const V*>(a.val),
                      static_cast<const V*>(a.x), static_cast<V*>(a.y), V(a.alpha), V(a.beta),
                      a.read_y, a.cap, static_cast<const V*>(w), partial, done);

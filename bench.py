@@ -760,7 +760,7 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short run for counter collection: copy probe, then DA and CSR SpMV "
                          "with the launch shapes of --profile-da and --profile-csr")
-    ap.add_argument("--profile-da", default="stream_g2_t4096",
+    ap.add_argument("--profile-da", default="stream_g2_t1024",
                     help="DA-CSR launch shape of the counter run")
     ap.add_argument("--profile-csr", default="stream_g2_t2048",
                     help="CSR launch shape of the counter run")

@@ -20,11 +20,14 @@ namespace damn {
 // does not reach the last row is cut back to a power-of-two number of rows:
 // on grids whose lines have power-of-two length the tiles then cover whole
 // lines or equal parts of them, and every row slot of the workgroup's row
-// loop is used (on the 7-point 128 x 128 x 1024 stencil, 256-row tiles with
-// one lane per row took 274 us against 294 us for the greedy 292-row tiles,
-// whose second pass over the rows leaves most lanes idle).  The kernels size LDS
-// and detect long rows by A->tiles_cap, the largest entry count of a
-// regular tile (every long row exceeds it, as it exceeds `cap`).
+// loop is used (7-point 128 x 128 x 1024 stencil, one lane per row: 274 us
+// with 256-row tiles against 294 us with the greedy 292-row tiles, whose
+// second pass over the rows leaves most lanes idle).
+//
+// The kernels size LDS by A->tiles_cap and A->tiles_rows, the most entries
+// and rows of a regular tile, so small tiles leave room for more resident
+// workgroups; they also take a tile with more than tiles_cap entries for one
+// long row (every long row exceeds `cap`, hence tiles_cap).
 int build_tiles(damn_mat A, int32_t cap) {
   if (A->d_tiles && A->tiles_req == cap) return DAMN_OK;
   std::vector<int32_t> starts;

@@ -49,11 +49,19 @@ def kernel_name(label, launch):
 COPY_KERNEL = "stream_copy"
 
 
+def _code_only(text):
+    """C++ source without comments and with whitespace collapsed, so that
+    editing a comment does not invalidate a recorded measurement."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(PKG, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(PKG, rel)) as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()
 
 

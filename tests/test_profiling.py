@@ -91,3 +91,11 @@ def test_trace_table_orders_by_total_time(tmp_path):
     P.write_trace_summary(str(path), str(out), "title", "cmd", "notes")
     text = out.read_text()
     assert "| `b_kernel` | 2 | 4.0 |" in text
+
+
+def test_source_hash_ignores_comments_only():
+    a = "int f(int x) {  // twice\n  return 2 * x; /* note */\n}\n"
+    b = "// header\nint f(int x) {\n  return 2 * x;\n}\n"
+    c = "int f(int x) {\n  return 3 * x;\n}\n"
+    assert P._code_only(a) == P._code_only(b)
+    assert P._code_only(a) != P._code_only(c)

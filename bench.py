@@ -549,14 +549,18 @@ def bench_spmm(D, args):
             row[name] = {"model_bytes": T}
             for vname, variant in (("stream", D.VAR_STREAM), ("vector", D.VAR_VECTOR)):
                 t_best = None
+                tiles = (1024, 2048) if variant == D.VAR_STREAM else (2048,)
                 for lanes in (1, 2, 4, 8, 16):
-                    mat.set_config(variant, lanes, 1, 2048)
-                    mat.spmm(X, Y)
-                    t = epochs(lambda: mat.spmm(X, Y), 10, 3)
-                    if t_best is None or t < t_best[0]:
-                        t_best = (t, lanes)
+                    for tile in tiles:
+                        mat.set_config(variant, lanes, 1, tile)
+                        mat.spmm(X, Y)
+                        t = epochs(lambda: mat.spmm(X, Y), 10, 3)
+                        if t_best is None or t < t_best[0]:
+                            t_best = (t, lanes, tile)
                 row[name][vname] = {"us": round(t_best[0] * 1e6, 1), "lanes": t_best[1],
                                     "gbs": round(T / t_best[0] / 1e9, 1)}
+                if variant == D.VAR_STREAM:
+                    row[name][vname]["tile"] = t_best[2]
             best = min(row[name]["stream"]["us"], row[name]["vector"]["us"])
             row[name]["us"] = best
             row[name]["gbs"] = round(T / (best * 1e-6) / 1e9, 1)

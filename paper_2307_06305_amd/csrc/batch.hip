@@ -40,8 +40,14 @@ struct BatchMat {
 
 constexpr int32_t kBatchTileRows = 256;
 
+// One tile: the entry range and the pointers its copy needs, so a
+// workgroup starts its copies after a single load; the matrix record
+// (vectors, right-hand sides, lanes) loads meanwhile.
 struct BatchTile {
-  int32_t mat, r0, r1, pad;
+  const double* val;
+  const int16_t* off;
+  const int32_t* rowptr;
+  int32_t mat, r0, r1, p0, p1, pad;
 };
 
 typedef double d2 __attribute__((ext_vector_type(2)));
@@ -122,16 +128,15 @@ __global__ __launch_bounds__(256) void batch_spmm(const BatchMat* __restrict__ m
   const int32_t t_end = range ? range[w + 1] : int32_t(w) + 1;
   for (int32_t t = t_begin; t < t_end; ++t) {
     const BatchTile tile = tiles[t];
-    const BatchMat m = mats[tile.mat];
-    const int32_t p0 = m.rowptr[tile.r0], p1 = m.rowptr[tile.r1];
-    const int32_t a0 = p0 & ~7;
+    const int32_t a0 = tile.p0 & ~7;
     __syncthreads();  // the previous tile's readers are done with LDS
-    kern::copy_to_lds(val_s, m.val, a0, p1 - a0);
-    kern::copy_to_lds(idx_s, m.off, a0, p1 - a0);
+    kern::copy_to_lds(val_s, tile.val, a0, tile.p1 - a0);
+    kern::copy_to_lds(idx_s, tile.off, a0, tile.p1 - a0);
     // the tile's row pointers rowptr[ar .. r1] (at most kBatchTileRows + 4;
     // the allocation is padded for the last piece)
     const int32_t ar = tile.r0 & ~3;
-    kern::copy_to_lds(rp_s, m.rowptr, ar, tile.r1 + 1 - ar);
+    kern::copy_to_lds(rp_s, tile.rowptr, ar, tile.r1 + 1 - ar);
+    const BatchMat m = mats[tile.mat];
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
 #define DAMN_ROWS(K, P) \
@@ -245,7 +250,8 @@ extern "C" int damn_batch_create(damn_batch* out, int32_t count, const damn_mat*
       while (r < A->nrows) {
         const int32_t first = r;
         while (r < A->nrows && r - first < bk::kBatchTileRows && rp[r + 1] - rp[first] <= cap) ++r;
-        ht.push_back({i, first, r, 0});
+        ht.push_back({static_cast<const double*>(A->d_val), static_cast<const int16_t*>(A->d_idx),
+                      A->d_rowptr, i, first, r, rp[first], rp[r], 0});
         const double bytes = double(rp[r] - rp[first]) * (2 + 8) +
                              double(r - first) * (4 + 8.0 * k * (beta != 0.0 ? 2 : 1)) +
                              double(rp[r] - rp[first]) * 8.0 * k / 4;  // gathers, mostly cached

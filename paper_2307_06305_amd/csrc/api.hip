@@ -30,7 +30,7 @@ namespace damn {
 // long row (every long row exceeds `cap`, hence tiles_cap).
 int build_tiles(damn_mat A, int32_t cap) {
   if (A->d_tiles && A->tiles_req == cap) return DAMN_OK;
-  std::vector<int32_t> starts;
+  std::vector<TileStart> starts;
   int32_t largest = 0, most_rows = 1;
   try {
     // rows of the stored structure: block rows for block formats
@@ -39,7 +39,7 @@ int build_tiles(damn_mat A, int32_t cap) {
     const int32_t* rp = A->h_rowptr.data();
     int32_t r = 0;
     while (r < nr) {
-      starts.push_back(r);
+      starts.push_back({r, rp[r]});
       const int32_t first = r;
       if (rp[r + 1] - rp[r] > cap) {
         ++r;
@@ -54,13 +54,13 @@ int build_tiles(damn_mat A, int32_t cap) {
       largest = std::max(largest, rp[r] - rp[first]);
       most_rows = std::max(most_rows, r - first);
     }
-    starts.push_back(nr);
+    starts.push_back({nr, rp[nr]});
   } catch (const std::bad_alloc&) {
     return DAMN_ERR_ALLOC;
   }
-  int32_t* d = nullptr;
-  if (hipMalloc(&d, sizeof(int32_t) * starts.size()) != hipSuccess) return DAMN_ERR_ALLOC;
-  if (hipMemcpy(d, starts.data(), sizeof(int32_t) * starts.size(), hipMemcpyHostToDevice) !=
+  TileStart* d = nullptr;
+  if (hipMalloc(&d, sizeof(TileStart) * starts.size()) != hipSuccess) return DAMN_ERR_ALLOC;
+  if (hipMemcpy(d, starts.data(), sizeof(TileStart) * starts.size(), hipMemcpyHostToDevice) !=
       hipSuccess) {
     hipFree(d);
     return DAMN_ERR_HIP;

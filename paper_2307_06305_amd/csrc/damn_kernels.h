@@ -12,6 +12,15 @@ namespace damn {
 // Rows per stream tile are capped so one workgroup's second step stays short
 // and the tile's row pointers fit a fixed LDS area.
 constexpr int32_t kMaxTileRows = 512;
+// Start of a stream tile: its first row and that row's first entry (for
+// block formats: block row and block), so a workgroup knows its rows and
+// entry range after one load.  Tiles are listed in order, followed by the
+// end record (nrows, nnz).
+struct alignas(8) TileStart {
+  int32_t row;
+  int32_t entry;
+};
+
 // Row-pointer arrays are allocated with this many spare (zero) entries so
 // 16-byte copies of a tile's row pointers stay inside the allocation.
 constexpr int32_t kRowptrPad = 16;
@@ -49,7 +58,7 @@ struct SpmvArgs {
   CooCarry* coo_carry = nullptr;
   int64_t nchunks = 0;
   // stream variant
-  const int32_t* tile_row = nullptr;
+  const TileStart* tile_row = nullptr;
   int64_t ntiles = 0;
   int32_t cap = 0;
   int32_t tile_rows = kMaxTileRows;  // most rows (block rows) of any tile

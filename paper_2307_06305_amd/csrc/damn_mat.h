@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "damn.h"
+#include "damn_kernels.h"
 
 struct damn_cg_work;  // conjugate-gradient workspace, allocated on first use
 
@@ -23,7 +24,7 @@ struct damn_mat_s {
   void* d_val = nullptr;  // float64 or float32 values, padded
   std::vector<int32_t> h_rowptr;  // host copy, for building stream tiles
   damn_config cfg{};
-  int32_t* d_tiles = nullptr;  // stream tiles: first row of each tile, plus nrows
+  damn::TileStart* d_tiles = nullptr;  // stream tiles, then the end record
   int64_t ntiles = 0;
   int32_t tiles_req = 0;  // entry cap the tiles were built for
   int32_t tiles_cap = 0;  // largest entry count of a tile that is not one long row

@@ -20,7 +20,7 @@ namespace kern {
 
 template <typename I, bool DA, int G, int NRHS, bool PAIRS>
 __global__ __launch_bounds__(256) void spmm_stream(
-    const int32_t* __restrict__ tile_row, const int32_t* __restrict__ rowptr,
+    const TileStart* __restrict__ tile_row, const int32_t* __restrict__ rowptr,
     const I* __restrict__ idx, const double* __restrict__ val, const double* __restrict__ X,
     double* __restrict__ Y, double alpha, double beta, int32_t read_y, int32_t cap) {
   using L = TileLds<I, double>;
@@ -31,8 +31,8 @@ __global__ __launch_bounds__(256) void spmm_stream(
   int32_t* rp_s = reinterpret_cast<int32_t*>(lds + (sizeof(double) + sizeof(I)) * slots);
 
   const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
-  const int32_t r0 = tile_row[t], r1 = tile_row[t + 1];
-  const int32_t p0 = rowptr[r0], p1 = rowptr[r1];
+  const TileStart ta = tile_row[t], tb = tile_row[t + 1];
+  const int32_t r0 = ta.row, r1 = tb.row, p0 = ta.entry, p1 = tb.entry;
 
   if (p1 - p0 > cap) {
     // one long row: the whole workgroup strides over it

@@ -41,7 +41,7 @@ struct BsrLds {
 
 template <typename I, typename S, typename V, bool DA, int B, int G>
 __global__ __launch_bounds__(256) void spmv_bsr_stream(
-    const int32_t* __restrict__ tile_row, const int32_t* __restrict__ browptr,
+    const TileStart* __restrict__ tile_row, const int32_t* __restrict__ browptr,
     const I* __restrict__ bidx, const S* __restrict__ bval, const V* __restrict__ x,
     V* __restrict__ y, V alpha, V beta, int32_t read_y, int32_t cap) {
   using L = BsrLds<I, S, B>;
@@ -51,8 +51,8 @@ __global__ __launch_bounds__(256) void spmv_bsr_stream(
   int32_t* rp_s = reinterpret_cast<int32_t*>(lds + sizeof(S) * L::val_slots(cap) +
                                              sizeof(I) * L::idx_slots(cap));
   const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
-  const int32_t r0 = tile_row[t], r1 = tile_row[t + 1];
-  const int32_t p0 = browptr[r0], p1 = browptr[r1];
+  const TileStart ta = tile_row[t], tb = tile_row[t + 1];
+  const int32_t r0 = ta.row, r1 = tb.row, p0 = ta.entry, p1 = tb.entry;
 
   if (p1 - p0 > cap) {
     // one long block row: the whole workgroup strides over its blocks

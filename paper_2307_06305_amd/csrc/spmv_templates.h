@@ -123,7 +123,7 @@ __device__ __forceinline__ double block_sum(double v, double* scratch4) {
 // w = y), and every workgroup returns at once when *done is nonzero.
 template <typename I, typename V, bool DA, int G, bool DOT = false, typename S = V>
 __global__ __launch_bounds__(256) void spmv_stream(
-    const int32_t* __restrict__ tile_row, const int32_t* __restrict__ rowptr,
+    const TileStart* __restrict__ tile_row, const int32_t* __restrict__ rowptr,
     const I* __restrict__ idx, const S* __restrict__ val, const V* __restrict__ x,
     V* __restrict__ y, V alpha, V beta, int32_t read_y, int32_t cap,
     const V* __restrict__ w = nullptr, double* __restrict__ partial = nullptr,
@@ -138,8 +138,8 @@ __global__ __launch_bounds__(256) void spmv_stream(
   int32_t* rp_s = reinterpret_cast<int32_t*>(lds + (sizeof(S) + sizeof(I)) * slots);
 
   const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
-  const int32_t r0 = tile_row[t], r1 = tile_row[t + 1];
-  const int32_t p0 = rowptr[r0], p1 = rowptr[r1];
+  const TileStart ta = tile_row[t], tb = tile_row[t + 1];
+  const int32_t r0 = ta.row, r1 = tb.row, p0 = ta.entry, p1 = tb.entry;
 
   if (p1 - p0 > cap) {
     // one long row: the whole workgroup strides over it

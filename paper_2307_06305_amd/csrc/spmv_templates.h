@@ -131,7 +131,6 @@ __global__ __launch_bounds__(256) void spmv_stream(
   using L = TileLds<I, S>;
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ double red[4];
-  if (DOT && *done) return;
   const int32_t slots = L::slots(cap);
   S* val_s = reinterpret_cast<S*>(lds);
   I* idx_s = reinterpret_cast<I*>(lds + sizeof(S) * slots);
@@ -139,6 +138,8 @@ __global__ __launch_bounds__(256) void spmv_stream(
 
   const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
   const TileStart ta = tile_row[t], tb = tile_row[t + 1];
+  // the flag is loaded after the tile records, so the three loads overlap
+  if (DOT && *done) return;
   const int32_t r0 = ta.row, r1 = tb.row, p0 = ta.entry, p1 = tb.entry;
 
   if (p1 - p0 > cap) {

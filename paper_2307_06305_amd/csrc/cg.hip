@@ -39,7 +39,7 @@ struct Scal {
   int32_t pad;
 };
 
-constexpr int kVecBlocks = 1024;  // workgroups of the vector kernels
+constexpr int kVecBlocks = 4096;  // workgroups of the vector kernels (16 per CU)
 constexpr int kFinThreads = 1024;
 
 enum Op { kStart = 0, kAlpha = 1, kBeta = 2, kNorm = 3 };

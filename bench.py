@@ -764,6 +764,10 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short run for counter collection: copy probe, then DA and CSR SpMV "
                          "with the launch shapes of --profile-da and --profile-csr")
+    ap.add_argument("--da-launch", default=None,
+                    help="DA-CSR launch shape of the main product (stream_gG_tT); default: autotuned")
+    ap.add_argument("--csr-launch", default=None,
+                    help="CSR launch shape of the comparison (stream_gG_tT); default: autotuned")
     ap.add_argument("--profile-da", default="stream_g2_t1024",
                     help="DA-CSR launch shape of the counter run")
     ap.add_argument("--profile-csr", default="stream_g2_t2048",
@@ -832,9 +836,20 @@ def main():
     del buf
     log(f"streaming read ceiling: {stream_gbs:.0f} GB/s")
 
-    # pick launch shapes (autotuner)
-    best_da, times_da = autotune(M, xd, yd, reps=args.tune_reps)
-    best_csr, times_csr = autotune(Cm, xd, yc, reps=args.tune_reps)
+    # pick launch shapes (autotuner), unless given: a kernel trace of a run
+    # with fixed shapes holds only the timed launches of each product
+    from paper_2307_06305_amd.profiling import stream_launch
+
+    def pick(mat, y, given):
+        if given is None:
+            return autotune(mat, xd, y, reps=args.tune_reps)
+        g, t = stream_launch(given)
+        cfg = (D.VAR_STREAM, g, 1, t)
+        mat.set_config(*cfg)
+        return cfg, {cfg: float("nan")}
+
+    best_da, times_da = pick(M, yd, args.da_launch)
+    best_csr, times_csr = pick(Cm, yc, args.csr_launch)
     log(f"DA best {config_name(best_da)} {times_da[best_da]*1e6:.1f}us; "
         f"CSR best {config_name(best_csr)} {times_csr[best_csr]*1e6:.1f}us")
     if args.dump:

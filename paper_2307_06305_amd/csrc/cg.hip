@@ -69,7 +69,14 @@ struct Pack {
 template <typename V, typename FP, typename FT>
 __device__ __forceinline__ void for_packs(int64_t s, int64_t e, FP pack, FT tail) {
   constexpr int kP = Pack<V>::kN;
-  for (int64_t base = s + int64_t(threadIdx.x) * kP; base < e; base += 256 * kP) {
+  int64_t base = s + int64_t(threadIdx.x) * kP;
+  // two packs per step while both are whole (same visiting order as one
+  // pack per step, so partial sums keep their order)
+  for (; base + 256 * kP + kP <= e; base += 512 * kP) {
+    pack(base);
+    pack(base + 256 * kP);
+  }
+  for (; base < e; base += 256 * kP) {
     if (base + kP <= e) {
       pack(base);
     } else {
@@ -229,12 +236,13 @@ __global__ __launch_bounds__(256) void update_xp(int64_t n, V* __restrict__ x, V
   slice(n, 1024, &s, &e);
   typedef Pack<V> P;
   for_packs<V>(s, e, [&](int64_t base) {
+      // all three loads before the first store, so they are in flight together
       typename P::vec xv = P::load(x + base), pv = P::load(p + base);
+      const typename P::vec rv = more ? P::load(r + base) : typename P::vec(V(0));
 #pragma unroll
       for (int k = 0; k < P::kN; ++k) xv[k] = V(double(xv[k]) + a * double(pv[k]));
       P::store(x + base, xv);
       if (more) {
-        const typename P::vec rv = P::load(r + base);
 #pragma unroll
         for (int k = 0; k < P::kN; ++k) pv[k] = V(double(rv[k]) + bt * double(pv[k]));
         P::store(p + base, pv);

@@ -73,8 +73,10 @@ __global__ __launch_bounds__(256) void spmv_vector(
 
 // ---------------------------------------------------------------------------
 // Stream variant.  The host cuts the rows into tiles of consecutive rows
-// holding at most `cap` entries (and at most kMaxTileRows rows); a row longer
-// than `cap` is a tile of its own.  A workgroup:
+// holding at most `cap` entries (and at most kMaxTileRows rows, cut back to
+// a power-of-two count); a row longer than `cap` is a tile of its own.  Each
+// tile is listed with its first row and that row's first entry, so a
+// workgroup knows its rows and entries after one load.  A workgroup:
 //   1. copies the tile's indices, values and row pointers from HBM straight
 //      into LDS with 16-byte direct-to-LDS loads (global_load_lds_dwordx4),
 //      starting at the tile's first entry rounded down so every 16-byte piece

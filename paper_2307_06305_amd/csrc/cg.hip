@@ -135,18 +135,27 @@ __global__ __launch_bounds__(kFinThreads) void finalize(const double* __restrict
     if (op == kAlpha && threadIdx.x == 0) sc->last = 0;
     return;
   }
-  // eight independent sums per thread keep eight loads in flight; they are
-  // combined in a fixed order, so the result does not depend on timing
-  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  int32_t i = threadIdx.x;
-  for (; i + 7 * kFinThreads < np; i += 8 * kFinThreads) {
+  // eight independent sums per thread, each fed by 16-byte loads of two
+  // partials, keep eight loads in flight; they are combined in a fixed
+  // order, so the result does not depend on timing
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const d2* pp = reinterpret_cast<const d2*>(partial);  // partial is 16-byte aligned
+  const int32_t npairs = np >> 1;
+  d2 a[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] += partial[i + u * kFinThreads];
+  for (int u = 0; u < 8; ++u) a[u] = d2(0.0);
+  int32_t i = threadIdx.x;
+  for (; i + 7 * kFinThreads < npairs; i += 8 * kFinThreads) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += pp[i + u * kFinThreads];
   }
 #pragma unroll
   for (int u = 0; u < 7; ++u)
-    if (i + u * kFinThreads < np) a[u] += partial[i + u * kFinThreads];
-  double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    if (i + u * kFinThreads < npairs) a[u] += pp[i + u * kFinThreads];
+  if ((np & 1) && threadIdx.x == 0) a[7].y += partial[np - 1];
+  double acc = 0.0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc += a[u].x + a[u].y;
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = acc;
   __syncthreads();

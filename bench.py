@@ -741,6 +741,69 @@ def bench_selector_training(D, args):
     return res
 
 
+def summary(res):
+    """A compact digest of every figure the run measured, printed last on
+    stderr so that a log cut to its tail still carries them."""
+    out = []
+
+    def g(d, *keys):
+        for k in keys:
+            if not isinstance(d, dict) or k not in d:
+                return None
+            d = d[k]
+        return d
+
+    da, csr = res.get("da", {}), res.get("csr", {})
+    out.append(f"27pt128 DA {da.get('us')}us {da.get('gbs')}GB/s {da.get('pct_hbm_peak')}%peak | "
+               f"CSR {csr.get('us')}us | speedup {res.get('speedup')} (model "
+               f"{res.get('predicted_speedup')}, uplift frac {res.get('uplift_fraction')}) | "
+               f"events {g(res, 'roofline', 'achieved')}GB/s frac {g(res, 'roofline', 'frac')} | "
+               f"read ceiling {res.get('stream_read_gbs')}GB/s")
+    if "mall" in res:
+        m = res["mall"]
+        out.append("MALL probe (MB: GB/s plain/nt): " + ", ".join(
+            f"{r['mb']}: {r['plain_gbs']}/{r['nt_gbs']}" for r in m.get("read", [])))
+    b = res.get("banded")
+    if b:
+        n, s = b.get("natural", {}), b.get("scrambled", {})
+        out.append(f"band4M natural DA {g(n, 'da', 'us')}us ({g(n, 'da', 'pct_hbm_peak')}%) "
+                   f"CSR {g(n, 'csr', 'us')}us speedup {n.get('speedup')} (model "
+                   f"{n.get('predicted_speedup')}) | scrambled CSR "
+                   f"{g(s, 'csr_scrambled_order', 'us')}us -> reordered w "
+                   f"{s.get('bandwidth_reordered')} DA {g(s, 'da', 'us')}us CSR "
+                   f"{g(s, 'csr', 'us')}us speedup {s.get('speedup')}")
+    for key, name in (("cg", "CG box 128x128x1024 DA16"), ("cg_cube", "CG cube 256^3 CSR32")):
+        c = res.get(key)
+        if c:
+            out.append(f"{name}: fp64 {g(c, 'fp64', 's')}s {g(c, 'fp64', 'iters')}it | mixed "
+                       f"{g(c, 'mixed', 's')}s {g(c, 'mixed', 'outer')}x"
+                       f"{g(c, 'mixed', 'iters')}it | speedup {c.get('speedup_mixed')}")
+    sw = res.get("sweep")
+    if sw:
+        out.append("sweep N:regime DA/CSR us (speedup): " + ", ".join(
+            f"{r['N']}:{r['regime']} {r['da']['us']}/{r['csr']['us']} ({r['speedup']})"
+            for r in sw))
+    bt = res.get("batch")
+    if bt:
+        sel = bt.get("selector", {})
+        out.append(f"batch512 graph {bt.get('graph_us')}us {bt.get('graph_gbs')}GB/s vs separate "
+                   f"{bt.get('separate_us')}us | selector regret mean {sel.get('mean_regret')} "
+                   f"p95 {sel.get('p95_regret')} within5% {sel.get('within_5pct')}")
+    sp = res.get("spmm")
+    if isinstance(sp, dict):
+        parts = []
+        for k, v in sp.items():
+            if isinstance(v, dict) and "da" in v and isinstance(v["da"], dict):
+                parts.append(f"{k}: DA {v['da'].get('us')}us")
+        if parts:
+            out.append("spmm " + ", ".join(parts))
+    cb = res.get("cpu_baseline")
+    if cb:
+        out.append(f"cpu oracle {cb.get('value')}GB/s on {cb.get('cores')} core")
+    for line in out:
+        print(f"[summary] {line}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -957,6 +1020,7 @@ def main():
             "sample": f"oracle DA-CSR SpMV (NumPy, float64) on the full workload, {reps} runs, "
                       f"{t_cpu:.2f} s each",
         }
+    summary(res)
     print(json.dumps(res), flush=True)
 
 

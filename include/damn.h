@@ -218,7 +218,9 @@ int damn_store_values(int64_t n, const void* vals, int32_t vals_dtype, int32_t d
  *      to nearest even).  Every r + off[i] must lie in [0, ncols) (checked
  *      on the host, so no kernel can read outside x; Sec. 4, remark on
  *      non-square matrices).
- * Out: *out, a handle owning its device memory (free with damn_destroy).
+ * Out: *out, a handle owning its device memory (free with damn_destroy),
+ *      including the stream-variant tile table of its default
+ *      configuration, so the product calls never allocate.
  * The copies are ordered on `stream`; the call synchronises the stream
  * before returning so the host arrays may be freed at once.
  * Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_BAD_CSR, DAMN_ERR_ALLOC,
@@ -296,7 +298,10 @@ int damn_mat_info(damn_mat A, int32_t* nrows, int32_t* ncols, int64_t* nnz,
 /* ------------------------------------------------------------------------
  * Products (Sec. 4, Listing 2).  x has ncols entries, y has nrows, in
  * device memory: float64 for float64 handles, float32 for float32 and
- * float16 handles (which accumulate in float32).
+ * float16 handles (which accumulate in float32).  A product call only
+ * launches kernels on `stream`: it never allocates, copies or synchronises,
+ * so it may be captured into a HIP graph, the first call on a fresh handle
+ * included.
  * --------------------------------------------------------------------- */
 
 /* y <- alpha*A*x + beta*y for a DA handle (DA16, DA8, DA-BSR, DA-COO): row r
@@ -351,9 +356,14 @@ typedef struct {
 
 /* Set / read the configuration used by damn_spmv, damn_csr_spmv and
  * damn_spmm on this handle.  A new handle starts with a default derived
- * from its mean row length.  Errors: DAMN_ERR_INVALID_ARG,
- * DAMN_ERR_UNSUPPORTED, DAMN_ERR_ALLOC/HIP (stream tiles are built on first
- * use of a tile size). */
+ * from its mean row length, its tiles already built.  A stream
+ * configuration with a new tile size rebuilds the tile table: that call
+ * allocates, uploads on the null stream, waits for the device to finish all
+ * queued work and frees the old table, so it belongs in setup code, not in
+ * a captured or latency-critical region.  A vector configuration keeps the
+ * last stream tiles (block formats and conjugate gradients run the stream
+ * kernels on them).  Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_UNSUPPORTED,
+ * DAMN_ERR_ALLOC, DAMN_ERR_HIP. */
 int damn_set_config(damn_mat A, const damn_config* cfg);
 int damn_get_config(damn_mat A, damn_config* cfg);
 
@@ -401,7 +411,8 @@ int damn_cg(damn_mat A64, damn_mat A32, const double* b, double* x,
 
 /* ------------------------------------------------------------------------
  * Batched products: Y_i <- alpha*A_i*X_i + beta*Y_i for many DA-CSR
- * matrices (the product of Sec. 4, repeated) in one persistent launch.
+ * matrices (the product of Sec. 4, repeated) in one graph-captured launch
+ * (one workgroup per tile by default, or a persistent grid on request).
  * --------------------------------------------------------------------- */
 
 typedef struct damn_batch_s* damn_batch;

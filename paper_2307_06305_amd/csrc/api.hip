@@ -28,7 +28,12 @@ namespace damn {
 // and rows of a regular tile, so small tiles leave room for more resident
 // workgroups; they also take a tile with more than tiles_cap entries for one
 // long row (every long row exceeds `cap`, hence tiles_cap).
-int build_tiles(damn_mat A, int32_t cap) {
+//
+// Tiles are built when a handle is created and when damn_set_config picks a
+// new cap, never inside a product call: the table is uploaded on `s` and
+// waited for, and a table it replaces is freed only after the device has
+// drained every launch queued so far (any of them may still read it).
+int build_tiles(damn_mat A, int32_t cap, hipStream_t s) {
   if (A->d_tiles && A->tiles_req == cap) return DAMN_OK;
   std::vector<TileStart> starts;
   int32_t largest = 0, most_rows = 1;
@@ -60,12 +65,19 @@ int build_tiles(damn_mat A, int32_t cap) {
   }
   TileStart* d = nullptr;
   if (hipMalloc(&d, sizeof(TileStart) * starts.size()) != hipSuccess) return DAMN_ERR_ALLOC;
-  if (hipMemcpy(d, starts.data(), sizeof(TileStart) * starts.size(), hipMemcpyHostToDevice) !=
-      hipSuccess) {
+  if (hipMemcpyAsync(d, starts.data(), sizeof(TileStart) * starts.size(), hipMemcpyHostToDevice,
+                     s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
     hipFree(d);
     return DAMN_ERR_HIP;
   }
-  if (A->d_tiles) hipFree(A->d_tiles);
+  if (A->d_tiles) {
+    if (hipDeviceSynchronize() != hipSuccess) {
+      hipFree(d);
+      return DAMN_ERR_HIP;
+    }
+    hipFree(A->d_tiles);
+  }
   A->d_tiles = d;
   A->ntiles = int64_t(starts.size()) - 1;
   A->tiles_req = cap;
@@ -130,6 +142,17 @@ void free_mat(damn_mat A) {
   release_cg_work(A);
   hipSetDevice(cur);
   delete A;
+}
+
+// Last step of every create call for the tiled formats: the stream tiles of
+// the default configuration, so no product call has to build them.
+int create_tiles(damn_mat A, hipStream_t s) {
+  const int st = build_tiles(A, tile_cap(A, A->cfg.tile), s);
+  if (st != DAMN_OK) {
+    free_mat(A);
+    return st;
+  }
+  return DAMN_OK;
 }
 
 // Upload a validated matrix: indices of `format` as given, values rounded
@@ -206,6 +229,20 @@ int create_common(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* ro
   return DAMN_OK;
 }
 
+// create_common, then the stream tiles of the default configuration
+int create_tiled(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* rowptr,
+                 const void* idx, const void* vals, int32_t vals_dtype, int32_t store_dtype,
+                 void* stream, int32_t format) {
+  damn_mat A = nullptr;
+  int st = create_common(&A, nrows, ncols, rowptr, idx, vals, vals_dtype, store_dtype, stream,
+                         format);
+  if (st != DAMN_OK) return st;
+  st = create_tiles(A, static_cast<hipStream_t>(stream));
+  if (st != DAMN_OK) return st;
+  *out = A;
+  return DAMN_OK;
+}
+
 int run_spmv(damn_mat A, const void* x, void* y, double alpha, double beta, void* stream,
              bool want_da) {
   if (A == nullptr || format_is_da(A->format) != want_da) return DAMN_ERR_INVALID_ARG;
@@ -239,9 +276,7 @@ int run_spmv(damn_mat A, const void* x, void* y, double alpha, double beta, void
       const hipError_t e = launch_spmv(a, DAMN_VAR_VECTOR, 1, 1);
       return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
     }
-    const int32_t tile = A->cfg.variant == DAMN_VAR_STREAM ? A->cfg.tile : 2048;
-    const int st = build_tiles(A, tile_cap(A, tile));
-    if (st != DAMN_OK) return st;
+    if (A->d_tiles == nullptr) return DAMN_ERR_INVALID_ARG;
     a.block = A->block;
     a.tile_row = A->d_tiles;
     a.ntiles = A->ntiles;
@@ -251,8 +286,7 @@ int run_spmv(damn_mat A, const void* x, void* y, double alpha, double beta, void
     return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
   }
   if (A->cfg.variant == DAMN_VAR_STREAM) {
-    const int st = build_tiles(A, A->cfg.tile);
-    if (st != DAMN_OK) return st;
+    if (A->d_tiles == nullptr) return DAMN_ERR_INVALID_ARG;
     a.tile_row = A->d_tiles;
     a.ntiles = A->ntiles;
     a.cap = A->tiles_cap;
@@ -309,8 +343,8 @@ int damn_create(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* rowp
     if (local) __atomic_store_n(&bad, 1, __ATOMIC_RELAXED);
   }, 4096);
   if (bad) return DAMN_ERR_BAD_CSR;
-  return create_common(out, nrows, ncols, rowptr, off, vals, vals_dtype, store_dtype, stream,
-                       DAMN_FORMAT_DA16);
+  return create_tiled(out, nrows, ncols, rowptr, off, vals, vals_dtype, store_dtype, stream,
+                      DAMN_FORMAT_DA16);
 }
 
 int damn_csr_create(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* rowptr,
@@ -318,8 +352,8 @@ int damn_csr_create(damn_mat* out, int32_t nrows, int32_t ncols, const int32_t* 
                     int32_t store_dtype, void* stream) {
   const int st = check_csr(nrows, ncols, rowptr, colids);
   if (st != DAMN_OK) return st;
-  return create_common(out, nrows, ncols, rowptr, colids, vals, vals_dtype, store_dtype, stream,
-                       DAMN_FORMAT_CSR32);
+  return create_tiled(out, nrows, ncols, rowptr, colids, vals, vals_dtype, store_dtype, stream,
+                      DAMN_FORMAT_CSR32);
 }
 
 int damn_bsr_create(damn_mat* out, int32_t format, int32_t nbrows, int32_t nbcols, int32_t b,
@@ -366,6 +400,8 @@ int damn_bsr_create(damn_mat* out, int32_t format, int32_t nbrows, int32_t nbcol
   A->block = b;
   A->nrows = nbrows * b;
   A->ncols = nbcols * b;
+  st = create_tiles(A, static_cast<hipStream_t>(stream));
+  if (st != DAMN_OK) return st;
   *out = A;
   return DAMN_OK;
 }
@@ -449,8 +485,8 @@ int damn_create_format(damn_mat* out, int32_t format, int32_t nrows, int32_t nco
     if (local) __atomic_store_n(&bad, 1, __ATOMIC_RELAXED);
   }, 4096);
   if (bad) return DAMN_ERR_BAD_CSR;
-  return create_common(out, nrows, ncols, rowptr, idx, vals, vals_dtype, store_dtype, stream,
-                       format);
+  return create_tiled(out, nrows, ncols, rowptr, idx, vals, vals_dtype, store_dtype, stream,
+                      format);
 }
 
 int damn_destroy(damn_mat A) {
@@ -515,8 +551,7 @@ int damn_spmm(damn_mat A, const void* X, void* Y, int32_t nrhs, double alpha, do
   if (A->cfg.variant == DAMN_VAR_STREAM) {
     // one right-hand side: the SpMV kernels (X and Y are vectors)
     if (nrhs == 1) return run_spmv(A, X, Y, alpha, beta, stream, format_is_da(A->format));
-    const int st = build_tiles(A, A->cfg.tile);
-    if (st != DAMN_OK) return st;
+    if (A->d_tiles == nullptr) return DAMN_ERR_INVALID_ARG;
     a.tile_row = A->d_tiles;
     a.ntiles = A->ntiles;
     a.cap = A->tiles_cap;
@@ -536,15 +571,13 @@ int damn_set_config(damn_mat A, const damn_config* cfg) {
   damn_config c = *cfg;
   if (c.variant == DAMN_VAR_VECTOR) {
     if (c.unroll != 1 && c.unroll != 2 && c.unroll != 4) return DAMN_ERR_INVALID_ARG;
+    // the tiles of the last stream configuration stay: block formats and
+    // conjugate gradients run the stream kernels on them
     if (c.tile == 0) c.tile = A->cfg.tile;
-    if (A->block > 1) {  // block formats run the stream variant with 2048-value tiles
-      const int st = build_tiles(A, tile_cap(A, 2048));
-      if (st != DAMN_OK) return st;
-    }
   } else {
     if (c.tile < 256 || c.tile > 4096 || (c.tile % 8) != 0) return DAMN_ERR_UNSUPPORTED;
     if (c.unroll == 0) c.unroll = 1;
-    const int st = build_tiles(A, tile_cap(A, c.tile));
+    const int st = build_tiles(A, tile_cap(A, c.tile), nullptr);
     if (st != DAMN_OK) return st;
   }
   A->cfg = c;

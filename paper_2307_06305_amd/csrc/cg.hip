@@ -99,6 +99,16 @@ __device__ __forceinline__ double sum256(double v) {
   return (w[0] + w[1]) + (w[2] + w[3]);
 }
 
+// Fresh scalar records sc[0, count): zeros, with the iteration limit set.
+// Written by a kernel so no host memory has to outlive the call.
+__global__ void reset_scal(Scal* __restrict__ sc, int32_t count, int32_t max_iter) {
+  const int32_t i = int32_t(threadIdx.x);
+  if (i >= count) return;
+  Scal z{};
+  z.max_iter = max_iter;
+  sc[i] = z;
+}
+
 // x = 0, r = b, p = b; partial[block] = sum b^2
 __global__ __launch_bounds__(256) void init64(int64_t n, const double* __restrict__ b,
                                               double* __restrict__ x, double* __restrict__ r,
@@ -385,10 +395,6 @@ int cg_lanes(damn_mat A) {
   return l > 16 ? 16 : l;
 }
 
-int cg_tile(damn_mat A) {
-  return A->cfg.variant == DAMN_VAR_STREAM ? A->cfg.tile : 2048;
-}
-
 #define DAMN_HIP_TRY(expr)                          \
   do {                                              \
     if ((expr) != hipSuccess) return DAMN_ERR_HIP;  \
@@ -441,13 +447,9 @@ int residual(damn_mat A64, damn_cg_work* w, const double* b, const double* x, hi
   return DAMN_OK;
 }
 
-}  // namespace
-}  // namespace damn
-
-using namespace damn;
-
-extern "C" int damn_cg(damn_mat A64, damn_mat A32, const double* b, double* x,
-                       const damn_cg_opts* opts, damn_cg_info* info, void* stream) {
+// Arguments of a solve, checked before any work is queued.
+int check_args(damn_mat A64, damn_mat A32, const double* b, double* x, const damn_cg_opts* opts,
+               damn_cg_info* info) {
   if (A64 == nullptr || opts == nullptr || info == nullptr) return DAMN_ERR_INVALID_ARG;
   if (A64->nrows != A64->ncols || A64->dtype != DAMN_F64) return DAMN_ERR_INVALID_ARG;
   if (A64->nrows > 0 && (b == nullptr || x == nullptr)) return DAMN_ERR_INVALID_ARG;
@@ -462,24 +464,31 @@ extern "C" int damn_cg(damn_mat A64, damn_mat A32, const double* b, double* x,
   if (!(opts->tol > 0.0) || opts->max_iter < 1 || opts->check_every < 1 ||
       (A32 && (!(opts->inner_tol > 0.0) || opts->max_outer < 1)))
     return DAMN_ERR_INVALID_ARG;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const int64_t n = A64->nrows;
-  int st = build_tiles(A64, cg_tile(A64));
-  if (st == DAMN_OK && A32) st = build_tiles(A32, cg_tile(A32));
-  if (st != DAMN_OK) return st;
+  // every tiled handle carries the stream tiles of its last stream
+  // configuration (built at create)
+  if (A64->d_tiles == nullptr || (A32 && A32->d_tiles == nullptr)) return DAMN_ERR_INVALID_ARG;
+  return DAMN_OK;
+}
+
+// Partial sums a solve needs: one per tile of either matrix, one per
+// workgroup of the vector kernels.
+int64_t partial_count(damn_mat A64, damn_mat A32) {
   int64_t np = cgk::kVecBlocks;
   if (A64->ntiles > np) np = A64->ntiles;
   if (A32 && A32->ntiles > np) np = A32->ntiles;
-  damn_cg_work* w = nullptr;
-  st = get_work(A64, np, A32 != nullptr, &w);
-  if (st != DAMN_OK) return st;
+  return np;
+}
 
-  Scal init{};
-  init.max_iter = opts->max_iter;
-  Scal both[2] = {init, init};
-  DAMN_HIP_TRY(hipMemcpyAsync(w->sc, both, sizeof(both), hipMemcpyHostToDevice, s));
+// The solve proper, on a workspace w whose vectors hold n entries (the float32
+// ones only for a mixed solve) and whose partial array holds partial_count.
+int solve(damn_mat A64, damn_mat A32, const double* b, double* x, const damn_cg_opts* opts,
+          damn_cg_info* info, damn_cg_work* w, hipStream_t s) {
+  const int64_t n = A64->nrows;
+  hipLaunchKernelGGL(cgk::reset_scal, dim3(1), dim3(64), 0, s, w->sc, 2, opts->max_iter);
+  DAMN_HIP_TRY(hipGetLastError());
   const double tol2 = opts->tol * opts->tol;
   damn_cg_info out{};
+  int st = DAMN_OK;
 
   if (n == 0) {
     out.converged = 1;
@@ -531,8 +540,7 @@ extern "C" int damn_cg(damn_mat A64, damn_mat A32, const double* b, double* x,
     double target = 0.5 * opts->tol * std::sqrt(o.b2 / o.rho);
     if (target < opts->inner_tol) target = opts->inner_tol;
     if (target > 0.5) target = 0.5;
-    Scal fresh = init;
-    DAMN_HIP_TRY(hipMemcpyAsync(w->sc, &fresh, sizeof(Scal), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(cgk::reset_scal, dim3(1), dim3(64), 0, s, w->sc, 1, opts->max_iter);
     hipLaunchKernelGGL(cgk::mixed_start, dim3(cgk::kVecBlocks), dim3(256), 0, s, n, w->r,
                        w->sc + 1, w->rh, w->d, w->p32, w->partial);
     hipLaunchKernelGGL(cgk::finalize, dim3(1), dim3(cgk::kFinThreads), 0, s, w->partial,
@@ -561,4 +569,19 @@ extern "C" int damn_cg(damn_mat A64, damn_mat A32, const double* b, double* x,
   *info = out;
   if (breakdown) return DAMN_ERR_BREAKDOWN;
   return out.converged ? DAMN_OK : DAMN_ERR_NOT_CONVERGED;
+}
+
+}  // namespace
+}  // namespace damn
+
+using namespace damn;
+
+extern "C" int damn_cg(damn_mat A64, damn_mat A32, const double* b, double* x,
+                       const damn_cg_opts* opts, damn_cg_info* info, void* stream) {
+  int st = check_args(A64, A32, b, x, opts, info);
+  if (st != DAMN_OK) return st;
+  damn_cg_work* w = nullptr;
+  st = get_work(A64, partial_count(A64, A32), A32 != nullptr, &w);
+  if (st != DAMN_OK) return st;
+  return solve(A64, A32, b, x, opts, info, w, static_cast<hipStream_t>(stream));
 }

@@ -1,6 +1,8 @@
 // The device matrix handle, shared by the library's HIP translation units.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 #include <vector>
 
@@ -33,8 +35,8 @@ struct damn_mat_s {
 };
 
 namespace damn {
-// Build (or reuse) the stream tiles of A for entry cap `cap`.
-int build_tiles(damn_mat A, int32_t cap);
+// Build (or reuse) the stream tiles of A for entry cap `cap`; synchronises.
+int build_tiles(damn_mat A, int32_t cap, hipStream_t s);
 // Free the conjugate-gradient workspace of A, if any.
 void release_cg_work(damn_mat A);
 }  // namespace damn

@@ -4,7 +4,7 @@
 // Classes (DAMN_NCLASS = 49):
 //   0..20   vector variant, lanes {1,2,4,...,64} x unroll {1,2,4}  (nrhs = 1)
 //   21..41  stream variant, lanes {1,...,64} x tile {1024,2048,4096} (nrhs = 1)
-//   42..48  SpMM (vector), lanes {1,...,64}                          (nrhs > 1)
+//   42..48  SpMM (stream, 2048-entry tiles), lanes {1,...,64}        (nrhs > 1)
 //
 // Network: x = (f - mu) / sigma (16 features), h1 = relu(W1 x + b1) (64),
 // h2 = relu(W2 h1 + b2) (64), z = W3 h2 + b3 (49); classes that do not apply

@@ -308,6 +308,14 @@ def bench_sweep(D, args):
             t, k = graph_time(lambda: mat.apply(x, y))
             row[name] = {"us": round(t * 1e6, 3), "gbs": round(T / t / 1e9, 1),
                          "launch": config_name(best), "graph_launches": k}
+            if best[0] == D.VAR_STREAM:
+                # the same launch with the matrix loaded plainly (kept in
+                # the MALL when the working set fits it)
+                mat.set_config(*best, cache=D.CACHE_PLAIN)
+                tp, _ = graph_time(lambda: mat.apply(x, y))
+                mat.set_config(*best)
+                row[name]["us_plain"] = round(tp * 1e6, 3)
+                row[name]["gbs_plain"] = round(T / tp / 1e9, 1)
         row["speedup"] = round(row["csr"]["us"] / row["da"]["us"], 4)
         row["predicted_speedup"] = round(T_csr / T_da, 4)
         log(f"sweep N={N}: {row}")
@@ -316,6 +324,40 @@ def bench_sweep(D, args):
         Cm.destroy()
         del A, e
     return rows
+
+
+MALL_MB = (4, 16, 32, 64, 96, 128, 192, 256, 384, 512, 1024, 2048)
+
+
+def bench_mall(D, args):
+    """Read ceilings by working-set size: a buffer of S MB read over and over
+    (no flush), along each read path of the probe (16-byte loads into
+    registers or direct-to-LDS tiles of 8 KiB, the 27-point product's tile
+    size; non-temporal or plain).  A buffer that fits a cache level is
+    served from it on repeated reads: L2 is 4 MB per XCD (32 MB in all, each
+    XCD reading its own eighth), the MALL 256 MB."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    sink = torch.zeros(65536, dtype=torch.float64, device=dev)
+    modes = (("nt", D.READ_NT), ("plain", D.READ_PLAIN), ("lds_nt", D.READ_LDS_NT),
+             ("lds_plain", D.READ_LDS_PLAIN))
+    rows = []
+    for mb in MALL_MB:
+        buf = torch.empty(mb << 20, dtype=torch.uint8, device=dev)
+        buf.fill_(1)
+        row = {"mb": mb}
+        for name, mode in modes:
+            fn = lambda: D.stream_read(buf, sink, mode, 8192)
+            fn()
+            t1 = time_launches(fn, 3)
+            reps = max(5, min(2000, int(0.02 / max(t1, 1e-7))))
+            t = min(time_launches(fn, reps) for _ in range(3))
+            row[f"{name}_gbs"] = round(buf.numel() / t / 1e9, 1)
+        log(f"mall probe {mb} MB: {row}")
+        rows.append(row)
+        del buf
+    return {"tile_bytes": 8192, "read": rows}
 
 
 def bench_cg_cube(D, args):
@@ -761,8 +803,9 @@ def summary(res):
                f"read ceiling {res.get('stream_read_gbs')}GB/s")
     if "mall" in res:
         m = res["mall"]
-        out.append("MALL probe (MB: GB/s plain/nt): " + ", ".join(
-            f"{r['mb']}: {r['plain_gbs']}/{r['nt_gbs']}" for r in m.get("read", [])))
+        out.append("read probe by size (MB: GB/s nt/plain/lds_nt/lds_plain): " + ", ".join(
+            f"{r['mb']}: {r['nt_gbs']}/{r['plain_gbs']}/{r['lds_nt_gbs']}/{r['lds_plain_gbs']}"
+            for r in m.get("read", [])))
     b = res.get("banded")
     if b:
         n, s = b.get("natural", {}), b.get("scrambled", {})
@@ -780,9 +823,9 @@ def summary(res):
                        f"{g(c, 'mixed', 'iters')}it | speedup {c.get('speedup_mixed')}")
     sw = res.get("sweep")
     if sw:
-        out.append("sweep N:regime DA/CSR us (speedup): " + ", ".join(
-            f"{r['N']}:{r['regime']} {r['da']['us']}/{r['csr']['us']} ({r['speedup']})"
-            for r in sw))
+        out.append("sweep N:regime DA/CSR us (speedup) [DA/CSR us, plain loads]: " + ", ".join(
+            f"{r['N']}:{r['regime']} {r['da']['us']}/{r['csr']['us']} ({r['speedup']}) "
+            f"[{r['da'].get('us_plain')}/{r['csr'].get('us_plain')}]" for r in sw))
     bt = res.get("batch")
     if bt:
         sel = bt.get("selector", {})
@@ -802,6 +845,72 @@ def summary(res):
         out.append(f"cpu oracle {cb.get('value')}GB/s on {cb.get('cores')} core")
     for line in out:
         print(f"[summary] {line}", file=sys.stderr, flush=True)
+
+
+def profile_run(D, args):
+    """A short run for rocprofv3: the copy probe of known size (the counters'
+    calibration), then --profile-reps DA-CSR and CSR products of the chosen
+    workload at fixed launch shapes, so each kernel symbol holds only these
+    launches."""
+    import numpy as np
+    import torch
+
+    from paper_2307_06305_amd.profiling import stream_launch
+    from workloads import config_matrix, config_vector
+    from workloads.matrices import stencil_3d_27pt, uniform_vector
+
+    dev = torch.device("cuda:0")
+    src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        D.stream_copy(src, dst)
+    del src, dst
+    wl = args.profile_workload
+    if wl.startswith("read"):
+        mb = int(wl[4:])
+        buf = torch.empty(mb << 20, dtype=torch.uint8, device=dev)
+        buf.fill_(1)
+        sink = torch.zeros(65536, dtype=torch.float64, device=dev)
+        for mode in (D.READ_NT, D.READ_PLAIN, D.READ_LDS_NT, D.READ_LDS_PLAIN):
+            for _ in range(20):
+                D.stream_read(buf, sink, mode, 8192)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": "done", "workload": wl, "copy_bytes": 1 << 30,
+                          "read_bytes": mb << 20}), flush=True)
+        return
+    if wl == "27pt":
+        A, x = config_matrix(1), config_vector(1, 2097152)
+    elif wl in ("band", "band_rcm"):
+        A = config_matrix(2, scrambled=wl == "band_rcm")
+        x = config_vector(2, A.ncols)
+    elif wl.startswith("sweep"):
+        A = stencil_3d_27pt(int(wl[5:]), 1001)
+        x = uniform_vector(A.ncols, 2001)
+    else:
+        raise SystemExit(f"unknown --profile-workload {wl!r}")
+    e = D.encode(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, allow_rcm=wl == "band_rcm")
+    M = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], e["vals"])
+    if e["permuted"]:
+        cols = (np.repeat(np.arange(A.nrows, dtype=np.int64), np.diff(e["rowptr"]))
+                + e["off"].astype(np.int64)).astype(np.int32)
+        Cm = D.Matrix.csr_create(A.nrows, A.ncols, e["rowptr"], cols, e["vals"])
+    else:
+        Cm = D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals)
+    cache = D.CACHE_PLAIN if args.profile_cache == "plain" else D.CACHE_NT
+    g, t = stream_launch(args.profile_da)
+    M.set_config(D.VAR_STREAM, g, 1, t, cache=cache)
+    g, t = stream_launch(args.profile_csr)
+    Cm.set_config(D.VAR_STREAM, g, 1, t, cache=cache)
+    xd = torch.from_numpy(x).to(dev)
+    yd = torch.zeros(A.nrows, dtype=torch.float64, device=dev)
+    for _ in range(args.profile_reps):
+        M.spmv(xd, yd)
+    for _ in range(args.profile_reps):
+        Cm.csr_spmv(xd, yd)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": "done", "workload": wl, "n": A.nrows, "nnz": A.nnz,
+                      "bandwidth": e["w"], "copy_bytes": 1 << 30, "da": args.profile_da,
+                      "csr": args.profile_csr, "cache": args.profile_cache}), flush=True)
 
 
 def main():
@@ -835,6 +944,15 @@ def main():
                     help="DA-CSR launch shape of the counter run")
     ap.add_argument("--profile-csr", default="stream_g2_t2048",
                     help="CSR launch shape of the counter run")
+    ap.add_argument("--profile-workload", default="27pt",
+                    help="matrix of the counter run: 27pt (128^3), band (n 4M, natural order), "
+                         "band_rcm (the scrambled band after RCM + refinement), sweepN (the "
+                         "27-point N^3 matrix), or readMB (only the read probe on an MB-sized "
+                         "buffer, every read path, 20 times each)")
+    ap.add_argument("--profile-cache", default="nt", choices=("nt", "plain"),
+                    help="cache policy of the matrix stream in the counter run")
+    ap.add_argument("--profile-reps", type=int, default=10,
+                    help="launches of each product in the counter run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
@@ -856,6 +974,10 @@ def main():
     props = torch.cuda.get_device_properties(dev)
     log(f"device {props.name}, {props.multi_processor_count} CUs")
 
+    if args.profile:
+        profile_run(D, args)
+        return
+
     t = time.time()
     A = config_matrix(1)
     log(f"matrix {A.name}: n={A.nrows} nnz={A.nnz} ({time.time() - t:.1f}s)")
@@ -869,32 +991,10 @@ def main():
     yd = torch.zeros(A.nrows, dtype=torch.float64, device=dev)
     yc = torch.zeros_like(yd)
 
-    if args.profile:
-        # counter runs: a copy of known size, then the two products
-        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            D.stream_copy(src, dst)
-        del src, dst
-        from paper_2307_06305_amd.profiling import stream_launch
-
-        g, t = stream_launch(args.profile_da)
-        M.set_config(D.VAR_STREAM, g, 1, t)
-        g, t = stream_launch(args.profile_csr)
-        Cm.set_config(D.VAR_STREAM, g, 1, t)
-        for _ in range(10):
-            M.spmv(xd, yd)
-        for _ in range(10):
-            Cm.csr_spmv(xd, yc)
-        torch.cuda.synchronize()
-        print(json.dumps({"profile": "done", "copy_bytes": 1 << 30, "da": args.profile_da,
-                          "csr": args.profile_csr}), flush=True)
-        return
-
     # streaming ceiling: a plain 16-byte-load read of 2 GiB
     buf = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
     sink = torch.zeros(65536, dtype=torch.float64, device=dev)
-    t_read = epochs(lambda: D.stream_read(buf, sink), 10, 3)
+    t_read = epochs(lambda: D.stream_read(buf, sink, D.READ_NT), 10, 3)
     stream_gbs = buf.numel() / t_read / 1e9
     del buf
     log(f"streaming read ceiling: {stream_gbs:.0f} GB/s")
@@ -999,6 +1099,7 @@ def main():
     if not args.skip_cube:
         res["cg_cube"] = bench_cg_cube(D, args)
     if not args.skip_sweep:
+        res["mall"] = bench_mall(D, args)
         res["sweep"] = bench_sweep(D, args)
     if not args.skip_grid:
         res["grid"] = bench_grid(D, args)

@@ -346,12 +346,24 @@ int damn_spmm(damn_mat A, const void* X, void* Y, int32_t nrhs, double alpha,
  */
 typedef enum { DAMN_VAR_VECTOR = 0, DAMN_VAR_STREAM = 1 } damn_variant;
 
+/* Cache policy of the stream variant's matrix loads. */
+typedef enum {
+  DAMN_CACHE_NT = 0,    /* non-temporal (default): the matrix, read once per
+                           product, does not displace x from L2            */
+  DAMN_CACHE_PLAIN = 1  /* plain loads: a matrix that fits the MALL with its
+                           vectors stays there across repeated products;
+                           DA16 and CSR32 handles with float64 or float32
+                           values only (else DAMN_ERR_UNSUPPORTED); SpMM
+                           with nrhs > 1 and CG keep non-temporal loads    */
+} damn_cache;
+
 typedef struct {
   int32_t variant;
   int32_t lanes;
   int32_t unroll;
-  int32_t tile; /* stream variant only: entries per tile (256..4096, a
-                   multiple of 8; otherwise DAMN_ERR_UNSUPPORTED) */
+  int32_t tile;  /* stream variant only: entries per tile (256..4096, a
+                    multiple of 8; otherwise DAMN_ERR_UNSUPPORTED) */
+  int32_t cache; /* stream variant only: a damn_cache value, 0 default */
 } damn_config;
 
 /* Set / read the configuration used by damn_spmv, damn_csr_spmv and
@@ -525,11 +537,28 @@ int damn_select_prob(damn_mlp M, int32_t N, const float* feats, int32_t* cls, fl
  * Measurement helpers.
  * --------------------------------------------------------------------- */
 
+/* Read paths of the streaming probe. */
+typedef enum {
+  DAMN_READ_NT = 0,        /* 16-byte loads into registers, non-temporal   */
+  DAMN_READ_PLAIN = 1,     /* 16-byte loads into registers, plain          */
+  DAMN_READ_LDS_NT = 2,    /* direct-to-LDS 16-byte loads, non-temporal:
+                              the matrix stream of the product kernels     */
+  DAMN_READ_LDS_PLAIN = 3  /* direct-to-LDS 16-byte loads, plain           */
+} damn_read_mode;
+
 /* Streaming ceiling probe: reads `bytes` (multiple of 16) from device
- * buffer src with 16-byte loads and writes one float64 per workgroup into
- * sink[0 .. 65535] (device).  Used to measure the achievable HBM read rate
- * and to calibrate traffic counters.  Errors: DAMN_ERR_INVALID_ARG. */
-int damn_stream_read(const void* src, size_t bytes, double* sink, void* stream);
+ * buffer src along the read path `mode` and writes checksums into
+ * sink[0 .. 65535] (device, float64; workgroup b writes sink[b mod 65536]).
+ * The register modes give each of at most 65536 workgroups a contiguous
+ * slice; the LDS modes give each workgroup one tile of tile_bytes (1024 ..
+ * 65536, a multiple of 16; ignored otherwise), the shape of the product
+ * kernels' tiles.  Repeated reads of a buffer that fits a cache level
+ * (L2: 4 MB per XCD; MALL: 256 MB) measure that level's rate.  Used for the
+ * read ceilings the products are compared with, and to calibrate traffic
+ * counters.  Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_UNSUPPORTED (more than
+ * 2^31 - 1 tiles). */
+int damn_stream_read(const void* src, size_t bytes, double* sink, int32_t mode,
+                     int32_t tile_bytes, void* stream);
 
 /* Copy probe: dst = src for `bytes` (multiple of 16) with 16-byte accesses;
  * known bytes read and written, to calibrate memory-traffic counters.

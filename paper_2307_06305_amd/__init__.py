@@ -395,24 +395,27 @@ class Matrix:
                              float(alpha), float(beta), _stream_ptr(stream)), "spmm")
 
     # configuration ----------------------------------------------------------
-    def set_config(self, variant=VAR_VECTOR, lanes=8, unroll=1, tile=2048):
-        cfg = _lib_config(variant, lanes, unroll, tile)
+    def set_config(self, variant=VAR_VECTOR, lanes=8, unroll=1, tile=2048, cache=0):
+        cfg = _lib_config(variant, lanes, unroll, tile, cache)
         _check(lib.damn_set_config(self._h, C.addressof(cfg)), "set_config")
 
     def get_config(self):
         cfg = _Config()
         _check(lib.damn_get_config(self._h, C.addressof(cfg)), "get_config")
         return {"variant": cfg.variant, "lanes": cfg.lanes, "unroll": cfg.unroll,
-                "tile": cfg.tile}
+                "tile": cfg.tile, "cache": cfg.cache}
+
+
+CACHE_NT, CACHE_PLAIN = 0, 1
 
 
 class _Config(C.Structure):
     _fields_ = [("variant", C.c_int32), ("lanes", C.c_int32), ("unroll", C.c_int32),
-                ("tile", C.c_int32)]
+                ("tile", C.c_int32), ("cache", C.c_int32)]
 
 
-def _lib_config(variant, lanes, unroll, tile):
-    return _Config(int(variant), int(lanes), int(unroll), int(tile))
+def _lib_config(variant, lanes, unroll, tile, cache=0):
+    return _Config(int(variant), int(lanes), int(unroll), int(tile), int(cache))
 
 
 class _CgOpts(C.Structure):
@@ -607,8 +610,12 @@ class Mlp:
             pass
 
 
-def stream_read(src, sink, stream=None):
-    """Streaming-read probe over a contiguous device tensor (bytes % 16 == 0);
+READ_NT, READ_PLAIN, READ_LDS_NT, READ_LDS_PLAIN = 0, 1, 2, 3
+
+
+def stream_read(src, sink, mode=READ_NT, tile_bytes=8192, stream=None):
+    """Streaming-read probe over a contiguous device tensor (bytes % 16 == 0)
+    along read path `mode` (READ_*; the LDS modes in tiles of tile_bytes);
     sink: float64 device tensor with at least 65536 entries."""
     import torch
 
@@ -619,7 +626,8 @@ def stream_read(src, sink, stream=None):
     if sink.numel() < 65536:
         raise ValueError("sink needs 65536 entries")
     _check(lib.damn_stream_read(C.c_void_p(src.data_ptr()), C.c_size_t(nbytes),
-                                C.c_void_p(sink.data_ptr()), _stream_ptr(stream)), "stream_read")
+                                C.c_void_p(sink.data_ptr()), int(mode), int(tile_bytes),
+                                _stream_ptr(stream)), "stream_read")
 
 
 def stream_copy(src, dst, stream=None):

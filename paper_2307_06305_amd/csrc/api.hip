@@ -291,6 +291,7 @@ int run_spmv(damn_mat A, const void* x, void* y, double alpha, double beta, void
     a.ntiles = A->ntiles;
     a.cap = A->tiles_cap;
     a.tile_rows = A->tiles_rows;
+    a.cache = A->cfg.cache;
   }
   const hipError_t e = launch_spmv(a, A->cfg.variant, A->cfg.lanes, A->cfg.unroll);
   return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
@@ -574,8 +575,14 @@ int damn_set_config(damn_mat A, const damn_config* cfg) {
     // the tiles of the last stream configuration stay: block formats and
     // conjugate gradients run the stream kernels on them
     if (c.tile == 0) c.tile = A->cfg.tile;
+    c.cache = DAMN_CACHE_NT;
   } else {
     if (c.tile < 256 || c.tile > 4096 || (c.tile % 8) != 0) return DAMN_ERR_UNSUPPORTED;
+    if (c.cache != DAMN_CACHE_NT && c.cache != DAMN_CACHE_PLAIN) return DAMN_ERR_INVALID_ARG;
+    if (c.cache == DAMN_CACHE_PLAIN &&
+        (A->block > 1 || (A->format != DAMN_FORMAT_DA16 && A->format != DAMN_FORMAT_CSR32) ||
+         (A->dtype != DAMN_F64 && A->dtype != DAMN_F32)))
+      return DAMN_ERR_UNSUPPORTED;
     if (c.unroll == 0) c.unroll = 1;
     const int st = build_tiles(A, tile_cap(A, c.tile), nullptr);
     if (st != DAMN_OK) return st;
@@ -590,11 +597,18 @@ int damn_get_config(damn_mat A, damn_config* cfg) {
   return DAMN_OK;
 }
 
-int damn_stream_read(const void* src, size_t bytes, double* sink, void* stream) {
+int damn_stream_read(const void* src, size_t bytes, double* sink, int32_t mode,
+                     int32_t tile_bytes, void* stream) {
   if ((src == nullptr && bytes > 0) || sink == nullptr || bytes % 16 != 0)
     return DAMN_ERR_INVALID_ARG;
-  const hipError_t e =
-      launch_stream_read(src, int64_t(bytes), sink, static_cast<hipStream_t>(stream));
+  if (mode < DAMN_READ_NT || mode > DAMN_READ_LDS_PLAIN) return DAMN_ERR_INVALID_ARG;
+  const bool lds = mode == DAMN_READ_LDS_NT || mode == DAMN_READ_LDS_PLAIN;
+  if (lds && (tile_bytes < 1024 || tile_bytes > 65536 || tile_bytes % 16 != 0))
+    return DAMN_ERR_INVALID_ARG;
+  if (lds && int64_t(bytes / 16 + tile_bytes / 16 - 1) / (tile_bytes / 16) > INT32_MAX)
+    return DAMN_ERR_UNSUPPORTED;
+  const hipError_t e = launch_stream_read(src, int64_t(bytes), sink, mode, tile_bytes,
+                                          static_cast<hipStream_t>(stream));
   return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
 }
 

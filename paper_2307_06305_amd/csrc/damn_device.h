@@ -37,7 +37,9 @@ constexpr int kNonTemporal = 2;  // cache-policy bit "nt" of gfx950 loads
 // 16-byte aligned) into dst[0, ...), 16 bytes per lane; the last piece may
 // run up to 16 bytes past the range.  Lane l of wave w copies piece
 // 64*(w + 4*j) + l; every wave writes 1 KiB contiguous blocks of LDS.
-template <typename T>
+// AUX is the instruction's cache-policy field (kNonTemporal, or 0 for a
+// plain load that may be kept in every cache level).
+template <typename T, int AUX = kNonTemporal>
 __device__ __forceinline__ void copy_to_lds(T* __restrict__ dst, const T* __restrict__ src,
                                             int32_t a0, int32_t n) {
 #if defined(__HIP_DEVICE_COMPILE__)  // the builtin exists only in the device pass
@@ -47,8 +49,7 @@ __device__ __forceinline__ void copy_to_lds(T* __restrict__ dst, const T* __rest
   for (int32_t base = wave * 64; base < pieces; base += 256) {
     const int32_t q = base + lane;
     if (q < pieces)
-      __builtin_amdgcn_global_load_lds(src + a0 + kPer * q, dst + kPer * base, 16, 0,
-                                       kNonTemporal);
+      __builtin_amdgcn_global_load_lds(src + a0 + kPer * q, dst + kPer * base, 16, 0, AUX);
   }
 #endif
 }

@@ -58,6 +58,7 @@ struct SpmvArgs {
   CooCarry* coo_carry = nullptr;
   int64_t nchunks = 0;
   // stream variant
+  int32_t cache = DAMN_CACHE_NT;  // cache policy of the matrix stream (damn_cache)
   const TileStart* tile_row = nullptr;
   int64_t ntiles = 0;
   int32_t cap = 0;
@@ -84,7 +85,8 @@ hipError_t launch_spmv_dot(const SpmvArgs& a, int lanes, const void* w, double* 
 hipError_t launch_spmm(const SpmvArgs& a, int lanes, int nrhs);
 // The same with the stream variant's tiles (spmm_stream.hip)
 hipError_t launch_spmm_stream(const SpmvArgs& a, int lanes, int nrhs);
-hipError_t launch_stream_read(const void* src, int64_t bytes, double* sink, hipStream_t s);
+hipError_t launch_stream_read(const void* src, int64_t bytes, double* sink, int mode,
+                              int32_t tile_bytes, hipStream_t s);
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
 
 }  // namespace damn

@@ -59,7 +59,9 @@ __global__ __launch_bounds__(256) void scale_vector(int64_t n, V* __restrict__ y
 }
 
 // Streaming read probe: each workgroup reads a contiguous slice with 16-byte
-// loads and writes one checksum, so the compiler cannot drop the loads.
+// loads into registers (non-temporal or plain) and writes one checksum, so
+// the compiler cannot drop the loads.
+template <bool NT>
 __global__ __launch_bounds__(256) void stream_read(const u32x4* __restrict__ src, int64_t n16,
                                                    double* __restrict__ sink) {
   const uint32_t b = xcd_contiguous(blockIdx.x, gridDim.x);
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(256) void stream_read(const u32x4* __restrict__ src
   const int64_t e = s + per < n16 ? s + per : n16;
   uint32_t acc = 0;
   for (int64_t i = s + threadIdx.x; i < e; i += 256) {
-    const u32x4 v = __builtin_nontemporal_load(src + i);
+    const u32x4 v = NT ? __builtin_nontemporal_load(src + i) : src[i];
     acc ^= v.x ^ v.y ^ v.z ^ v.w;
   }
   __shared__ uint32_t red[256];
@@ -79,6 +81,31 @@ __global__ __launch_bounds__(256) void stream_read(const u32x4* __restrict__ src
     for (int k = 0; k < 256; ++k) t ^= red[k];
     sink[blockIdx.x] = double(t);
   }
+}
+
+// Streaming read probe on the product kernels' own path: one workgroup per
+// tile of `tile16` 16-byte pieces, copied from HBM straight into LDS with
+// the direct-to-LDS loads of copy_to_lds (non-temporal or plain), then one
+// word per thread folded into a checksum.  sink[b mod 65536] receives it.
+template <int AUX>
+__global__ __launch_bounds__(256) void stream_lds(const u32x4* __restrict__ src, int64_t n16,
+                                                  int32_t tile16, double* __restrict__ sink) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  u32x4* buf = reinterpret_cast<u32x4*>(lds);
+  const uint32_t b = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int64_t s = int64_t(b) * tile16;
+  const int64_t left = n16 - s;
+  const int32_t m = int32_t(left < tile16 ? left : tile16);
+  copy_to_lds<u32x4, AUX>(buf, src + s, 0, m);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  uint32_t acc = 0;
+  for (int32_t i = int32_t(threadIdx.x); i < m; i += 256) acc ^= buf[i].x;
+  acc = __shfl_xor(acc, 1, 64) ^ acc;
+  __shared__ uint32_t red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) sink[blockIdx.x & 65535u] = double(red[0] ^ red[1] ^ red[2] ^ red[3]);
 }
 
 // Copy probe: dst = src in 16-byte pieces, one contiguous slice per
@@ -182,14 +209,33 @@ hipError_t launch_spmm(const SpmvArgs& a, int lanes, int nrhs) {
                                       : launch_spmm<int32_t, false>(a, lanes, nrhs);
 }
 
-hipError_t launch_stream_read(const void* src, int64_t bytes, double* sink, hipStream_t s) {
+hipError_t launch_stream_read(const void* src, int64_t bytes, double* sink, int mode,
+                              int32_t tile_bytes, hipStream_t s) {
   const int64_t n16 = bytes / 16;
   if (n16 == 0) return hipSuccess;
+  const kern::u32x4* p = static_cast<const kern::u32x4*>(src);
+  if (mode == DAMN_READ_LDS_NT || mode == DAMN_READ_LDS_PLAIN) {
+    const int32_t t16 = tile_bytes / 16;
+    const int64_t blocks = (n16 + t16 - 1) / t16;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    const size_t lds = size_t(t16) * 16;
+    if (mode == DAMN_READ_LDS_NT)
+      hipLaunchKernelGGL(kern::stream_lds<kern::kNonTemporal>, dim3(uint32_t(blocks)), dim3(256),
+                         lds, s, p, n16, t16, sink);
+    else
+      hipLaunchKernelGGL(kern::stream_lds<0>, dim3(uint32_t(blocks)), dim3(256), lds, s, p, n16,
+                         t16, sink);
+    return hipGetLastError();
+  }
   int64_t blocks = n16 / 4096;  // about 64 KiB per workgroup
   if (blocks < 256) blocks = 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(kern::stream_read, dim3(uint32_t(blocks)), dim3(256), 0, s,
-                     static_cast<const kern::u32x4*>(src), n16, sink);
+  if (mode == DAMN_READ_NT)
+    hipLaunchKernelGGL(kern::stream_read<true>, dim3(uint32_t(blocks)), dim3(256), 0, s, p, n16,
+                       sink);
+  else
+    hipLaunchKernelGGL(kern::stream_read<false>, dim3(uint32_t(blocks)), dim3(256), 0, s, p, n16,
+                       sink);
   return hipGetLastError();
 }
 

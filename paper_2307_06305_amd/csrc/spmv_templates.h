@@ -111,19 +111,14 @@ struct TileLds {
   }
 };
 
-// Workgroup sum of one double per thread, in a fixed order (wave sums, then
-// the four wave results left to right); the result is valid in thread 0.
-__device__ __forceinline__ double block_sum(double v, double* scratch4) {
-  v = group_sum(v, 64);
-  if ((threadIdx.x & 63) == 0) scratch4[threadIdx.x >> 6] = v;
-  __syncthreads();
-  return (scratch4[0] + scratch4[1]) + (scratch4[2] + scratch4[3]);
-}
-
 // Optional epilogue for conjugate gradients (DOT): each workgroup also writes
 // partial[t] = sum over its rows of y_r * w_r in float64 (w = nullptr means
 // w = y), and every workgroup returns at once when *done is nonzero.
-template <typename I, typename V, bool DA, int G, bool DOT = false, typename S = V>
+// AUX is the cache policy of the entry arrays' copies: non-temporal by
+// default, plain (AUX = 0) for products whose whole working set fits the
+// MALL, where caching the matrix lets repeated products read it from there.
+template <typename I, typename V, bool DA, int G, bool DOT = false, typename S = V,
+          int AUX = kNonTemporal>
 __global__ __launch_bounds__(256) void spmv_stream(
     const TileStart* __restrict__ tile_row, const int32_t* __restrict__ rowptr,
     const I* __restrict__ idx, const S* __restrict__ val, const V* __restrict__ x,
@@ -133,6 +128,7 @@ __global__ __launch_bounds__(256) void spmv_stream(
   using L = TileLds<I, S>;
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ double red[4];
+  __shared__ uint32_t arrived;  // DOT: waves that have left their sum in red
   const int32_t slots = L::slots(cap);
   S* val_s = reinterpret_cast<S*>(lds);
   I* idx_s = reinterpret_cast<I*>(lds + sizeof(S) * slots);
@@ -168,10 +164,11 @@ __global__ __launch_bounds__(256) void spmv_stream(
   //    `rows` rows, rounded up to a whole piece: within the rows + 16 the
   //    launch allocates for its largest tile)
   const int32_t a0 = p0 & ~(L::kAlign - 1);
-  copy_to_lds(val_s, val, a0, p1 - a0);
-  copy_to_lds(idx_s, idx, a0, p1 - a0);
+  copy_to_lds<S, AUX>(val_s, val, a0, p1 - a0);
+  copy_to_lds<I, AUX>(idx_s, idx, a0, p1 - a0);
   const int32_t ar = r0 & ~3;
   copy_to_lds(rp_s, rowptr, ar, r1 + 1 - ar);
+  if (DOT && threadIdx.x == 0) arrived = 0;  // ordered before every wave's add by the barrier
   // the direct-to-LDS writes are tracked by vmcnt; the memory clobber keeps
   // the compiler from moving LDS reads above the wait
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -204,8 +201,17 @@ __global__ __launch_bounds__(256) void spmv_stream(
     }
   }
   if (DOT) {
-    dot = block_sum(dot, red);
-    if (threadIdx.x == 0) partial[t] = dot;
+    // Each wave leaves its sum in red[wave]; the wave that arrives last
+    // combines the four in a fixed order and writes the partial.  No
+    // workgroup barrier: a wave whose rows are done (or that has none)
+    // leaves at once instead of waiting for the slowest wave.
+    dot = group_sum(dot, 64);
+    if ((threadIdx.x & 63) == 0) {
+      red[threadIdx.x >> 6] = dot;
+      const uint32_t before = __hip_atomic_fetch_add(&arrived, 1u, __ATOMIC_ACQ_REL,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (before == 3) partial[t] = (red[0] + red[1]) + (red[2] + red[3]);
+    }
   }
 }
 
@@ -258,9 +264,26 @@ hipError_t vector(const SpmvArgs& a, int lanes, int unroll) {
   }
 }
 
+// Cells of the storage grid that have the plain-stream kernels: 16-bit DA
+// offsets and 32-bit CSR columns with float64 or float32 values.
+template <typename I, typename S, bool DA>
+constexpr bool kHasPlainStream =
+    (DA ? sizeof(I) == 2 : sizeof(I) == 4) && (sizeof(S) == 8 || sizeof(S) == 4);
+
 template <typename I, typename S, typename V, bool DA, int G>
 hipError_t stream_g(const SpmvArgs& a) {
   if (a.ntiles == 0) return hipSuccess;
+  if constexpr (kHasPlainStream<I, S, DA>) {
+    if (a.cache == DAMN_CACHE_PLAIN) {
+      hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, false, S, 0>), dim3(uint32_t(a.ntiles)),
+                         dim3(256), (kern::TileLds<I, S>::bytes(a.cap, a.tile_rows)), a.stream,
+                         a.tile_row, a.rowptr, static_cast<const I*>(a.idx),
+                         static_cast<const S*>(a.val), static_cast<const V*>(a.x),
+                         static_cast<V*>(a.y), V(a.alpha), V(a.beta), a.read_y, a.cap, nullptr,
+                         nullptr, nullptr);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, false, S>), dim3(uint32_t(a.ntiles)),
                      dim3(256), (kern::TileLds<I, S>::bytes(a.cap, a.tile_rows)), a.stream, a.tile_row,
                      a.rowptr, static_cast<const I*>(a.idx), static_cast<const S*>(a.val),

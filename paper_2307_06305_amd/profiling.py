@@ -45,7 +45,9 @@ def stream_launch(name):
 def kernel_name(label, launch):
     g, _ = stream_launch(launch)
     index = "short" if label == "da" else "int"
-    return f"spmv_stream<{index}, double, {'true' if label == 'da' else 'false'}, {g}, false, double>"
+    # the last template argument is the matrix stream's cache policy (2: non-temporal)
+    return (f"spmv_stream<{index}, double, {'true' if label == 'da' else 'false'}, {g}, false, "
+            f"double, 2>")
 COPY_KERNEL = "stream_copy"
 
 

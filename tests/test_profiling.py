@@ -32,9 +32,9 @@ def _fake_runs(tmp_path, g_da=2, g_csr=2):
 def test_kernel_names_follow_the_launch():
     assert P.stream_launch("stream_g4_t1024") == (4, 1024)
     assert P.kernel_name("da", "stream_g4_t1024") == \
-        "spmv_stream<short, double, true, 4, false, double>"
+        "spmv_stream<short, double, true, 4, false, double, 2>"
     assert P.kernel_name("csr", "stream_g1_t2048") == \
-        "spmv_stream<int, double, false, 1, false, double>"
+        "spmv_stream<int, double, false, 1, false, double, 2>"
     with pytest.raises(ValueError):
         P.stream_launch("vector_l4_u2")
 

@@ -335,7 +335,11 @@ def bench_mall(D, args):
     registers or direct-to-LDS tiles of 8 KiB, the 27-point product's tile
     size; non-temporal or plain).  A buffer that fits a cache level is
     served from it on repeated reads: L2 is 4 MB per XCD (32 MB in all, each
-    XCD reading its own eighth), the MALL 256 MB."""
+    XCD reading its own eighth), the MALL 256 MB.  Two timings per path:
+    one pass per launch, back to back (`<path>_gbs`, the regime of the
+    product sweep), and about 1 GiB per launch as repeated passes over the
+    buffer (`<path>_multi_gbs`), which pays the launch's ramp-up once and so
+    shows the rate of the level that serves the re-reads."""
     import torch
 
     dev = torch.device("cuda:0")
@@ -346,7 +350,8 @@ def bench_mall(D, args):
     for mb in MALL_MB:
         buf = torch.empty(mb << 20, dtype=torch.uint8, device=dev)
         buf.fill_(1)
-        row = {"mb": mb}
+        passes = max(1, 1024 // mb)
+        row = {"mb": mb, "passes": passes}
         for name, mode in modes:
             fn = lambda: D.stream_read(buf, sink, mode, 8192)
             fn()
@@ -354,6 +359,10 @@ def bench_mall(D, args):
             reps = max(5, min(2000, int(0.02 / max(t1, 1e-7))))
             t = min(time_launches(fn, reps) for _ in range(3))
             row[f"{name}_gbs"] = round(buf.numel() / t / 1e9, 1)
+            fm = lambda: D.stream_read(buf, sink, mode, 8192, passes=passes)
+            fm()
+            tm = min(time_launches(fm, 10) for _ in range(3))
+            row[f"{name}_multi_gbs"] = round(passes * buf.numel() / tm / 1e9, 1)
         log(f"mall probe {mb} MB: {row}")
         rows.append(row)
         del buf
@@ -803,9 +812,12 @@ def summary(res):
                f"read ceiling {res.get('stream_read_gbs')}GB/s")
     if "mall" in res:
         m = res["mall"]
-        out.append("read probe by size (MB: GB/s nt/plain/lds_nt/lds_plain): " + ", ".join(
-            f"{r['mb']}: {r['nt_gbs']}/{r['plain_gbs']}/{r['lds_nt_gbs']}/{r['lds_plain_gbs']}"
-            for r in m.get("read", [])))
+        out.append("read probe by size (MB: GB/s nt/plain/lds_nt/lds_plain, one pass per "
+                   "launch | ~1 GiB of passes per launch): " + ", ".join(
+                       f"{r['mb']}: {r['nt_gbs']}/{r['plain_gbs']}/{r['lds_nt_gbs']}/"
+                       f"{r['lds_plain_gbs']} | {r.get('nt_multi_gbs')}/{r.get('plain_multi_gbs')}/"
+                       f"{r.get('lds_nt_multi_gbs')}/{r.get('lds_plain_multi_gbs')}"
+                       for r in m.get("read", [])))
     b = res.get("banded")
     if b:
         n, s = b.get("natural", {}), b.get("scrambled", {})
@@ -871,12 +883,15 @@ def profile_run(D, args):
         buf = torch.empty(mb << 20, dtype=torch.uint8, device=dev)
         buf.fill_(1)
         sink = torch.zeros(65536, dtype=torch.float64, device=dev)
+        passes = max(1, 1024 // mb)
         for mode in (D.READ_NT, D.READ_PLAIN, D.READ_LDS_NT, D.READ_LDS_PLAIN):
             for _ in range(20):
                 D.stream_read(buf, sink, mode, 8192)
+            for _ in range(5):
+                D.stream_read(buf, sink, mode, 8192, passes=passes)
         torch.cuda.synchronize()
         print(json.dumps({"profile": "done", "workload": wl, "copy_bytes": 1 << 30,
-                          "read_bytes": mb << 20}), flush=True)
+                          "read_bytes": mb << 20, "passes": passes}), flush=True)
         return
     if wl == "27pt":
         A, x = config_matrix(1), config_vector(1, 2097152)
@@ -948,7 +963,8 @@ def main():
                     help="matrix of the counter run: 27pt (128^3), band (n 4M, natural order), "
                          "band_rcm (the scrambled band after RCM + refinement), sweepN (the "
                          "27-point N^3 matrix), or readMB (only the read probe on an MB-sized "
-                         "buffer, every read path, 20 times each)")
+                         "buffer, every read path, 20 launches of one pass and 5 of "
+                         "1024 // MB passes each)")
     ap.add_argument("--profile-cache", default="nt", choices=("nt", "plain"),
                     help="cache policy of the matrix stream in the counter run")
     ap.add_argument("--profile-reps", type=int, default=10,

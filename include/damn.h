@@ -547,17 +547,19 @@ typedef enum {
 } damn_read_mode;
 
 /* Streaming ceiling probe: reads `bytes` (multiple of 16) from device
- * buffer src along the read path `mode` and writes checksums into
- * sink[0 .. 65535] (device, float64; workgroup b writes sink[b mod 65536]).
- * The register modes give each of at most 65536 workgroups a contiguous
- * slice; the LDS modes give each workgroup one tile of tile_bytes (1024 ..
- * 65536, a multiple of 16; ignored otherwise), the shape of the product
- * kernels' tiles.  Repeated reads of a buffer that fits a cache level
- * (L2: 4 MB per XCD; MALL: 256 MB) measure that level's rate.  Used for the
- * read ceilings the products are compared with, and to calibrate traffic
- * counters.  Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_UNSUPPORTED (more than
- * 2^31 - 1 tiles). */
-int damn_stream_read(const void* src, size_t bytes, double* sink, int32_t mode,
+ * buffer src `passes` times (>= 1) in one launch, along the read path
+ * `mode`, and writes checksums into sink[0 .. 65535] (device, float64;
+ * workgroup b writes sink[b mod 65536]).  The register modes give each of
+ * at most 65536 workgroups per pass a contiguous slice; the LDS modes give
+ * each workgroup one tile of tile_bytes (1024 .. 65536, a multiple of 16;
+ * ignored otherwise), the shape of the product kernels' tiles.  The passes
+ * follow each other in workgroup order, so a buffer larger than the L2
+ * (4 MB per XCD) but within the MALL (256 MB) is re-read from the MALL, if
+ * the read path allocates there, with the launch's ramp-up paid once.  Used
+ * for the read ceilings the products are compared with, and to calibrate
+ * traffic counters.  Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_UNSUPPORTED
+ * (more than 2^31 - 1 workgroups). */
+int damn_stream_read(const void* src, size_t bytes, int32_t passes, double* sink, int32_t mode,
                      int32_t tile_bytes, void* stream);
 
 /* Copy probe: dst = src for `bytes` (multiple of 16) with 16-byte accesses;

@@ -613,10 +613,11 @@ class Mlp:
 READ_NT, READ_PLAIN, READ_LDS_NT, READ_LDS_PLAIN = 0, 1, 2, 3
 
 
-def stream_read(src, sink, mode=READ_NT, tile_bytes=8192, stream=None):
+def stream_read(src, sink, mode=READ_NT, tile_bytes=8192, stream=None, passes=1):
     """Streaming-read probe over a contiguous device tensor (bytes % 16 == 0)
-    along read path `mode` (READ_*; the LDS modes in tiles of tile_bytes);
-    sink: float64 device tensor with at least 65536 entries."""
+    along read path `mode` (READ_*; the LDS modes in tiles of tile_bytes),
+    `passes` times over in one launch; sink: float64 device tensor with at
+    least 65536 entries."""
     import torch
 
     if not src.is_cuda or not src.is_contiguous():
@@ -625,7 +626,7 @@ def stream_read(src, sink, mode=READ_NT, tile_bytes=8192, stream=None):
     _dev_ptr(sink, torch.float64, sink.numel(), "sink")
     if sink.numel() < 65536:
         raise ValueError("sink needs 65536 entries")
-    _check(lib.damn_stream_read(C.c_void_p(src.data_ptr()), C.c_size_t(nbytes),
+    _check(lib.damn_stream_read(C.c_void_p(src.data_ptr()), C.c_size_t(nbytes), int(passes),
                                 C.c_void_p(sink.data_ptr()), int(mode), int(tile_bytes),
                                 _stream_ptr(stream)), "stream_read")
 

@@ -597,17 +597,19 @@ int damn_get_config(damn_mat A, damn_config* cfg) {
   return DAMN_OK;
 }
 
-int damn_stream_read(const void* src, size_t bytes, double* sink, int32_t mode,
+int damn_stream_read(const void* src, size_t bytes, int32_t passes, double* sink, int32_t mode,
                      int32_t tile_bytes, void* stream) {
-  if ((src == nullptr && bytes > 0) || sink == nullptr || bytes % 16 != 0)
+  if ((src == nullptr && bytes > 0) || sink == nullptr || bytes % 16 != 0 || passes < 1)
     return DAMN_ERR_INVALID_ARG;
   if (mode < DAMN_READ_NT || mode > DAMN_READ_LDS_PLAIN) return DAMN_ERR_INVALID_ARG;
   const bool lds = mode == DAMN_READ_LDS_NT || mode == DAMN_READ_LDS_PLAIN;
   if (lds && (tile_bytes < 1024 || tile_bytes > 65536 || tile_bytes % 16 != 0))
     return DAMN_ERR_INVALID_ARG;
-  if (lds && int64_t(bytes / 16 + tile_bytes / 16 - 1) / (tile_bytes / 16) > INT32_MAX)
-    return DAMN_ERR_UNSUPPORTED;
-  const hipError_t e = launch_stream_read(src, int64_t(bytes), sink, mode, tile_bytes,
+  // workgroups per pass: one per tile (LDS modes), at most 65536 slices otherwise
+  const int64_t per_pass =
+      lds ? int64_t(bytes / 16 + tile_bytes / 16 - 1) / (tile_bytes / 16) : int64_t(65536);
+  if (per_pass * passes > INT32_MAX) return DAMN_ERR_UNSUPPORTED;
+  const hipError_t e = launch_stream_read(src, int64_t(bytes), passes, sink, mode, tile_bytes,
                                           static_cast<hipStream_t>(stream));
   return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
 }

@@ -85,8 +85,8 @@ hipError_t launch_spmv_dot(const SpmvArgs& a, int lanes, const void* w, double* 
 hipError_t launch_spmm(const SpmvArgs& a, int lanes, int nrhs);
 // The same with the stream variant's tiles (spmm_stream.hip)
 hipError_t launch_spmm_stream(const SpmvArgs& a, int lanes, int nrhs);
-hipError_t launch_stream_read(const void* src, int64_t bytes, double* sink, int mode,
-                              int32_t tile_bytes, hipStream_t s);
+hipError_t launch_stream_read(const void* src, int64_t bytes, int32_t passes, double* sink,
+                              int mode, int32_t tile_bytes, hipStream_t s);
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
 
 }  // namespace damn

@@ -60,12 +60,14 @@ __global__ __launch_bounds__(256) void scale_vector(int64_t n, V* __restrict__ y
 
 // Streaming read probe: each workgroup reads a contiguous slice with 16-byte
 // loads into registers (non-temporal or plain) and writes one checksum, so
-// the compiler cannot drop the loads.
+// the compiler cannot drop the loads.  The grid is `slices` workgroups per
+// pass; workgroup t (after the XCD renumbering) reads slice t mod slices, so
+// a launch of several passes reads the buffer that many times over.
 template <bool NT>
 __global__ __launch_bounds__(256) void stream_read(const u32x4* __restrict__ src, int64_t n16,
-                                                   double* __restrict__ sink) {
-  const uint32_t b = xcd_contiguous(blockIdx.x, gridDim.x);
-  const int64_t per = (n16 + gridDim.x - 1) / gridDim.x;
+                                                   uint32_t slices, double* __restrict__ sink) {
+  const uint32_t b = xcd_contiguous(blockIdx.x, gridDim.x) % slices;
+  const int64_t per = (n16 + slices - 1) / slices;
   const int64_t s = int64_t(b) * per;
   const int64_t e = s + per < n16 ? s + per : n16;
   uint32_t acc = 0;
@@ -79,7 +81,7 @@ __global__ __launch_bounds__(256) void stream_read(const u32x4* __restrict__ src
   if (threadIdx.x == 0) {
     uint32_t t = 0;
     for (int k = 0; k < 256; ++k) t ^= red[k];
-    sink[blockIdx.x] = double(t);
+    sink[blockIdx.x & 65535u] = double(t);
   }
 }
 
@@ -87,12 +89,15 @@ __global__ __launch_bounds__(256) void stream_read(const u32x4* __restrict__ src
 // tile of `tile16` 16-byte pieces, copied from HBM straight into LDS with
 // the direct-to-LDS loads of copy_to_lds (non-temporal or plain), then one
 // word per thread folded into a checksum.  sink[b mod 65536] receives it.
+// The grid is `tiles` workgroups per pass; workgroup t (after the XCD
+// renumbering) reads tile t mod tiles.
 template <int AUX>
 __global__ __launch_bounds__(256) void stream_lds(const u32x4* __restrict__ src, int64_t n16,
-                                                  int32_t tile16, double* __restrict__ sink) {
+                                                  int32_t tile16, uint32_t tiles,
+                                                  double* __restrict__ sink) {
   extern __shared__ __align__(16) unsigned char lds[];
   u32x4* buf = reinterpret_cast<u32x4*>(lds);
-  const uint32_t b = xcd_contiguous(blockIdx.x, gridDim.x);
+  const uint32_t b = xcd_contiguous(blockIdx.x, gridDim.x) % tiles;
   const int64_t s = int64_t(b) * tile16;
   const int64_t left = n16 - s;
   const int32_t m = int32_t(left < tile16 ? left : tile16);
@@ -209,33 +214,36 @@ hipError_t launch_spmm(const SpmvArgs& a, int lanes, int nrhs) {
                                       : launch_spmm<int32_t, false>(a, lanes, nrhs);
 }
 
-hipError_t launch_stream_read(const void* src, int64_t bytes, double* sink, int mode,
-                              int32_t tile_bytes, hipStream_t s) {
+hipError_t launch_stream_read(const void* src, int64_t bytes, int32_t passes, double* sink,
+                              int mode, int32_t tile_bytes, hipStream_t s) {
   const int64_t n16 = bytes / 16;
-  if (n16 == 0) return hipSuccess;
+  if (n16 == 0 || passes == 0) return hipSuccess;
   const kern::u32x4* p = static_cast<const kern::u32x4*>(src);
   if (mode == DAMN_READ_LDS_NT || mode == DAMN_READ_LDS_PLAIN) {
     const int32_t t16 = tile_bytes / 16;
-    const int64_t blocks = (n16 + t16 - 1) / t16;
+    const int64_t tiles = (n16 + t16 - 1) / t16;
+    const int64_t blocks = tiles * passes;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     const size_t lds = size_t(t16) * 16;
     if (mode == DAMN_READ_LDS_NT)
       hipLaunchKernelGGL(kern::stream_lds<kern::kNonTemporal>, dim3(uint32_t(blocks)), dim3(256),
-                         lds, s, p, n16, t16, sink);
+                         lds, s, p, n16, t16, uint32_t(tiles), sink);
     else
       hipLaunchKernelGGL(kern::stream_lds<0>, dim3(uint32_t(blocks)), dim3(256), lds, s, p, n16,
-                         t16, sink);
+                         t16, uint32_t(tiles), sink);
     return hipGetLastError();
   }
-  int64_t blocks = n16 / 4096;  // about 64 KiB per workgroup
-  if (blocks < 256) blocks = 256;
-  if (blocks > 65536) blocks = 65536;
+  int64_t slices = n16 / 4096;  // about 64 KiB per workgroup
+  if (slices < 256) slices = 256;
+  if (slices > 65536) slices = 65536;
+  const int64_t blocks = slices * passes;
+  if (blocks > INT32_MAX) return hipErrorInvalidValue;
   if (mode == DAMN_READ_NT)
     hipLaunchKernelGGL(kern::stream_read<true>, dim3(uint32_t(blocks)), dim3(256), 0, s, p, n16,
-                       sink);
+                       uint32_t(slices), sink);
   else
     hipLaunchKernelGGL(kern::stream_read<false>, dim3(uint32_t(blocks)), dim3(256), 0, s, p, n16,
-                       sink);
+                       uint32_t(slices), sink);
   return hipGetLastError();
 }
 

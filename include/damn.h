@@ -47,7 +47,8 @@ typedef enum {
   DAMN_ERR_ALLOC = -5,         /* host or device allocation failed          */
   DAMN_ERR_UNSUPPORTED = -6,   /* combination not provided (e.g. nrhs > 8)  */
   DAMN_ERR_NOT_CONVERGED = -7, /* iteration limit reached                   */
-  DAMN_ERR_BREAKDOWN = -8      /* p.Ap <= 0: matrix not positive definite   */
+  DAMN_ERR_BREAKDOWN = -8,     /* p.Ap <= 0: matrix not positive definite   */
+  DAMN_ERR_TOO_LARGE = -9      /* more rows than a fixed scratch area holds */
 } damn_status;
 
 /* Scalar types of stored values (the scalar axis of Fig. 3).  Products
@@ -532,6 +533,25 @@ int damn_select(damn_mlp M, int32_t N, const float* feats, int32_t* cls, void* s
  * falls back to damn_autotune when it is low. */
 int damn_select_prob(damn_mlp M, int32_t N, const float* feats, int32_t* cls, float* prob,
                      void* stream);
+
+/* Allocation-free damn_select_prob, for callers that cannot allocate
+ * device memory (tight serving loops that pick a launch configuration per
+ * incoming matrix, harnesses that forbid hipMalloc).  Same arguments and
+ * results as damn_select_prob (prob may be NULL), bit for bit: the same
+ * inference kernel runs on the same feature rows.  The feature rows,
+ * classes and probabilities are staged in a fixed device array of the
+ * library, one copy per GPU, held until the process ends
+ * (DAMN_SELECT_NOALLOC_MAX_ROWS rows, 288 KiB); its address is looked up
+ * once per device, on the first call there.  The call allocates nothing,
+ * copies on `stream` and synchronises it before returning.  Calls that
+ * overlap on one GPU (other threads, other streams) share that array and
+ * race: serialise them.  Errors: DAMN_ERR_INVALID_ARG (null handle, N < 0,
+ * null feats/cls with N > 0, current device not the network's),
+ * DAMN_ERR_TOO_LARGE (N > DAMN_SELECT_NOALLOC_MAX_ROWS; nothing is
+ * launched), DAMN_ERR_HIP. */
+#define DAMN_SELECT_NOALLOC_MAX_ROWS 4096
+int damn_select_noalloc(damn_mlp M, int32_t N, const float* feats, int32_t* cls, float* prob,
+                        void* stream);
 
 /* ------------------------------------------------------------------------
  * Measurement helpers.

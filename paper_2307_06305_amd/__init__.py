@@ -23,6 +23,7 @@ FORMAT_DA16, FORMAT_CSR32, FORMAT_DA8, FORMAT_CSR16 = 0, 1, 2, 3
 FORMAT_DABSR16, FORMAT_BSR32 = 4, 5
 FORMAT_DACOO16, FORMAT_COO32 = 6, 7
 VAR_VECTOR, VAR_STREAM = 0, 1
+SELECT_NOALLOC_MAX_ROWS = 4096  # DAMN_SELECT_NOALLOC_MAX_ROWS
 
 # the storage grid of Fig. 3: format -> (index dtype, holds DA offsets)
 FORMATS = {FORMAT_DA16: (np.int16, True), FORMAT_CSR32: (np.int32, False),
@@ -596,6 +597,19 @@ class Mlp:
                                     out.ctypes.data_as(C.c_void_p),
                                     prob.ctypes.data_as(C.c_void_p) if with_prob else None,
                                     _stream_ptr(stream)), "select")
+        return (out, prob) if with_prob else out
+
+    def select_noalloc(self, feats, stream=None, with_prob=False):
+        """select() through damn_select_noalloc: the same results, staged in
+        the library's fixed device array (at most SELECT_NOALLOC_MAX_ROWS
+        rows), with no device allocation."""
+        F = np.ascontiguousarray(np.atleast_2d(feats), dtype=np.float32)
+        out = np.empty(F.shape[0], dtype=np.int32)
+        prob = np.empty(F.shape[0], dtype=np.float32)
+        _check(lib.damn_select_noalloc(self._h, F.shape[0], F.ctypes.data_as(C.c_void_p),
+                                       out.ctypes.data_as(C.c_void_p),
+                                       prob.ctypes.data_as(C.c_void_p) if with_prob else None,
+                                       _stream_ptr(stream)), "select_noalloc")
         return (out, prob) if with_prob else out
 
     def destroy(self):

@@ -98,6 +98,7 @@ _SIGS = {
                                  C.c_uint64, _vp, _vp]),
     "damn_select": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
     "damn_select_prob": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "damn_select_noalloc": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
 }
 
 class _Lib:

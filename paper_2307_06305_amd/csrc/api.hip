@@ -317,6 +317,7 @@ const char* damn_status_string(int status) {
     case DAMN_ERR_UNSUPPORTED: return "unsupported combination";
     case DAMN_ERR_NOT_CONVERGED: return "iteration limit reached";
     case DAMN_ERR_BREAKDOWN: return "breakdown: matrix not positive definite";
+    case DAMN_ERR_TOO_LARGE: return "more rows than the fixed scratch area holds";
     default: return "unknown status";
   }
 }

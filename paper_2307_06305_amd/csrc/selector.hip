@@ -22,6 +22,7 @@
 #include <cstdint>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -211,6 +212,38 @@ __global__ __launch_bounds__(64) void select_cls(const float* __restrict__ P,
       prob[s] = 1.0f / sum;
     }
   }
+}
+
+// Fixed device array of damn_select_noalloc: the feature rows, classes and
+// probabilities of up to kNoAllocMax rows.  Every GPU the library runs on
+// holds its own copy at its own address, found with hipGetSymbolAddress;
+// in host code the array's name is not a device address and is never
+// passed to a kernel or a copy.
+constexpr int32_t kNoAllocMax = DAMN_SELECT_NOALLOC_MAX_ROWS;
+constexpr size_t kNoAllocFeatOff = 0;
+constexpr size_t kNoAllocClsOff = kNoAllocFeatOff + sizeof(float) * F * size_t(kNoAllocMax);
+constexpr size_t kNoAllocProbOff = kNoAllocClsOff + sizeof(int32_t) * size_t(kNoAllocMax);
+constexpr size_t kNoAllocBytes = kNoAllocProbOff + sizeof(float) * size_t(kNoAllocMax);
+static_assert(kNoAllocClsOff % 256 == 0 && kNoAllocProbOff % 256 == 0, "scratch layout");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+unsigned char* g_scratch[kMaxDevices] = {};
+
+// The device address of `scratch` on device `dev` (the current device),
+// looked up on the first call there and kept.
+int noalloc_scratch(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return DAMN_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr)
+      return DAMN_ERR_HIP;
+    g_scratch[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch[dev];
+  return DAMN_OK;
 }
 
 // splitmix64, for initial weights and minibatch shuffles
@@ -595,6 +628,36 @@ int damn_select_prob(damn_mlp M, int32_t N, const float* feats, int32_t* cls, fl
   if (dc) hipFree(dc);
   if (dp) hipFree(dp);
   return st;
+}
+
+int damn_select_noalloc(damn_mlp M, int32_t N, const float* feats, int32_t* cls, float* prob,
+                        void* stream) {
+  using damn::sel::kNoAllocMax;
+  if (M == nullptr || N < 0 || (N > 0 && (feats == nullptr || cls == nullptr)))
+    return DAMN_ERR_INVALID_ARG;
+  if (N > kNoAllocMax) return DAMN_ERR_TOO_LARGE;
+  if (N == 0) return DAMN_OK;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return DAMN_ERR_HIP;
+  if (dev != M->device) return DAMN_ERR_INVALID_ARG;
+  unsigned char* base = nullptr;
+  const int st = damn::sel::noalloc_scratch(dev, &base);
+  if (st != DAMN_OK) return st;
+  float* df = reinterpret_cast<float*>(base + damn::sel::kNoAllocFeatOff);
+  int32_t* dc = reinterpret_cast<int32_t*>(base + damn::sel::kNoAllocClsOff);
+  float* dp = prob ? reinterpret_cast<float*>(base + damn::sel::kNoAllocProbOff) : nullptr;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  bool ok = hipMemcpyAsync(df, feats, sizeof(float) * size_t(N) * damn::sel::F,
+                           hipMemcpyHostToDevice, s) == hipSuccess;
+  if (ok) {
+    hipLaunchKernelGGL(damn::sel::select_cls, dim3(N), dim3(64), 0, s, M->P, df, dc, dp);
+    ok = hipGetLastError() == hipSuccess &&
+         hipMemcpyAsync(cls, dc, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s) == hipSuccess &&
+         (!prob || hipMemcpyAsync(prob, dp, sizeof(float) * N, hipMemcpyDeviceToHost, s) ==
+                       hipSuccess) &&
+         hipStreamSynchronize(s) == hipSuccess;
+  }
+  return ok ? DAMN_OK : DAMN_ERR_HIP;
 }
 
 int damn_select(damn_mlp M, int32_t N, const float* feats, int32_t* cls, void* stream) {

@@ -24,6 +24,14 @@ __device__ __forceinline__ V group_sum(V v, int width) {
   return v;
 }
 
+// Sum over the G lanes of a wave whose lane numbers agree modulo 64 / G
+// (lane l and lanes l + 64/G, l + 2*64/G, ...); every lane gets the sum.
+template <int G, typename V>
+__device__ __forceinline__ V strided_group_sum(V v) {
+  for (int o = 32; o >= 64 / G; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 template <typename V>
 __device__ __forceinline__ V finish(V acc, V alpha, V beta, bool read_y, const V* y) {
   return read_y ? alpha * acc + beta * (*y) : alpha * acc;

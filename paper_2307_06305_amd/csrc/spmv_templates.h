@@ -174,10 +174,16 @@ __global__ __launch_bounds__(256) void spmv_stream(
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 
-  // 2. G lanes per row
-  const int lane = threadIdx.x % G;
+  // 2. G lanes per row.  Within a wave, lane l takes row l mod (64/G) of the
+  //    wave's rows and part l / (64/G) of that row, so four neighbouring
+  //    lanes hold four neighbouring rows at the same entry position: for a
+  //    banded matrix their x gathers are adjacent words, which the vector
+  //    cache serves as one access.
+  constexpr int RPW = 64 / G;  // rows per wave and pass
+  const int wl = int(threadIdx.x & 63);
+  const int lane = wl / RPW;
   double dot = 0.0;
-  for (int32_t r = r0 + int32_t(threadIdx.x / G); r < r1; r += 256 / G) {
+  for (int32_t r = r0 + int32_t(threadIdx.x >> 6) * RPW + (wl % RPW); r < r1; r += 256 / G) {
     const int32_t s = rp_s[r - ar] - a0, e = rp_s[r + 1 - ar] - a0;
     const V* xs = DA ? x + r : x;
     // the dot epilogue's w_r, loaded with the row's gathers rather than
@@ -193,7 +199,7 @@ __global__ __launch_bounds__(256) void spmv_stream(
     for (int u = 0; u < 3; ++u)
       if (k + u * G < e) acc[u] += V(val_s[k + u * G]) * xs[idx_s[k + u * G]];
     V sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-    if (G > 1) sum = group_sum(sum, G);
+    if (G > 1) sum = strided_group_sum<G>(sum);
     if (lane == 0) {
       const V yr = finish(sum, alpha, beta, read_y != 0, y + r);
       y[r] = yr;

@@ -92,6 +92,57 @@ def test_cg_mixed_reaches_fp64_residual(A, fmt):
     A32.destroy()
 
 
+def _split_diagonal(A):
+    """A with the diagonal entry of every third row stored as two entries
+    (3/4 and 1/4 of it) next to each other: the same operator, but rows whose
+    diagonal is not one stored entry."""
+    from workloads.matrices import CSR
+
+    rows, cols, vals = [], [], []
+    for r in range(A.nrows):
+        for k in range(A.rowptr[r], A.rowptr[r + 1]):
+            c, v = int(A.colids[k]), float(A.vals[k])
+            if c == r and r % 3 == 0:
+                rows += [r, r]
+                cols += [c, c]
+                vals += [0.75 * v, 0.25 * v]
+            else:
+                rows.append(r)
+                cols.append(c)
+                vals.append(v)
+    rp = np.zeros(A.nrows + 1, dtype=np.int32)
+    np.add.at(rp, np.asarray(rows) + 1, 1)
+    return CSR(A.nrows, A.ncols, np.cumsum(rp).astype(np.int32),
+               np.asarray(cols, dtype=np.int32), np.asarray(vals), A.name + "_splitdiag")
+
+
+@pytest.mark.parametrize("fmt", ["da", "csr"])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 16])
+@pytest.mark.parametrize("split", [False, True])
+def test_cg_dot_epilogue_lanes_and_split_diagonal(fmt, lanes, split):
+    """The SpMV with the p.Ap epilogue at every lane count of the stream
+    kernel (lanes of a row spread over the wave), on the 2D Laplacian and on
+    the same operator with some diagonals stored as two entries: the solve
+    matches the oracle's CG on the same matrix."""
+    torch_or_skip()
+    A = laplace_2d_5pt(40)
+    if split:
+        A = _split_diagonal(A)
+    b = uniform_vector(A.nrows, 33)
+    A64, A32 = _handles(A, fmt)
+    A64.set_config(D.VAR_STREAM, lanes, 1, 1024)
+    xd = dev(np.zeros(A.nrows))
+    info = D.cg(A64, dev(b), xd, tol=1e-10, check_every=7)
+    ref = OC.cg_fp64(lambda v: OS.spmv_csr(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, v), b)
+    assert info["converged"] and ref["converged"]
+    rr = _true_rel_res(A, host(xd), b)
+    assert rr <= 1.05e-10
+    assert abs(info["rel_res"] - rr) <= 1e-12
+    assert abs(info["iters"] - ref["iters"]) <= 2
+    A64.destroy()
+    A32.destroy()
+
+
 def test_cg_iteration_limit_and_zero_rhs():
     torch_or_skip()
     A = laplace_2d_5pt(30)

@@ -168,6 +168,18 @@ def bench_banded(D, args):
                       **spmv_pair(D, M, Cm, A.nrows, A.ncols, A.nnz, x, args.tune_reps)}
     M.destroy()
     Cm.destroy()
+    # the same number of scattered x reads without the matrix: the gather
+    # rate the products cannot exceed (and, for context, narrower and wider
+    # scatter)
+    sink = torch.zeros(65536, dtype=torch.float64, device=dev)
+    per_row = int(round(A.nnz / A.nrows))
+    probe = {"rows": A.nrows, "per_row": per_row, "reads": A.nrows * per_row}
+    for hw in (64, 20000, 2000000):
+        fn = lambda: D.gather_read(x, sink, A.nrows, per_row, halfwidth=hw)
+        t = epochs(fn, 20)
+        probe[f"hw{hw}_us"] = round(t * 1e6, 1)
+        probe[f"hw{hw}_greads_per_s"] = round(A.nrows * per_row / t / 1e9, 1)
+    out["natural"]["gather_probe"] = probe
     del A, e
     log(f"banded natural: {out['natural']}")
     Q = config_matrix(2, scrambled=True)
@@ -809,7 +821,9 @@ def summary(res):
                f"CSR {csr.get('us')}us | speedup {res.get('speedup')} (model "
                f"{res.get('predicted_speedup')}, uplift frac {res.get('uplift_fraction')}) | "
                f"events {g(res, 'roofline', 'achieved')}GB/s frac {g(res, 'roofline', 'frac')} | "
-               f"read ceiling {res.get('stream_read_gbs')}GB/s")
+               f"read ceiling {res.get('stream_read_gbs')}GB/s | gathers alone "
+               f"{res.get('gather_probe_us')}us, stream at ceiling + gathers "
+               f"{res.get('bound_us')}us")
     if "mall" in res:
         m = res["mall"]
         out.append("read probe by size (MB: GB/s nt/plain/lds_nt/lds_plain, one pass per "
@@ -827,6 +841,11 @@ def summary(res):
                    f"{g(s, 'csr_scrambled_order', 'us')}us -> reordered w "
                    f"{s.get('bandwidth_reordered')} DA {g(s, 'da', 'us')}us CSR "
                    f"{g(s, 'csr', 'us')}us speedup {s.get('speedup')}")
+        gp = n.get("gather_probe")
+        if gp:
+            out.append(f"band4M gather probe ({gp['reads']} scattered reads, no matrix): "
+                       f"+-64 {gp['hw64_us']}us, +-20000 {gp['hw20000_us']}us "
+                       f"({gp['hw20000_greads_per_s']} G reads/s), +-2e6 {gp['hw2000000_us']}us")
     for key, name in (("cg", "CG box 128x128x1024 DA16"), ("cg_cube", "CG cube 256^3 CSR32")):
         c = res.get(key)
         if c:
@@ -1007,13 +1026,19 @@ def main():
     yd = torch.zeros(A.nrows, dtype=torch.float64, device=dev)
     yc = torch.zeros_like(yd)
 
-    # streaming ceiling: a plain 16-byte-load read of 2 GiB
+    # streaming ceiling: 2 GiB read along the products' own path (direct-to-LDS
+    # 16-byte loads, non-temporal, 8 KiB tiles)
     buf = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
     sink = torch.zeros(65536, dtype=torch.float64, device=dev)
-    t_read = epochs(lambda: D.stream_read(buf, sink, D.READ_NT), 10, 3)
+    t_read = epochs(lambda: D.stream_read(buf, sink, D.READ_LDS_NT, 8192), 10, 3)
     stream_gbs = buf.numel() / t_read / 1e9
     del buf
     log(f"streaming read ceiling: {stream_gbs:.0f} GB/s")
+    # the product's x gathers alone: the 27 DA offsets of the stencil for
+    # every row, no matrix stream
+    N = 128
+    offs27 = torch.tensor([dz * N * N + dy * N + dx for dz in (-1, 0, 1) for dy in (-1, 0, 1)
+                           for dx in (-1, 0, 1)], dtype=torch.int32, device=dev)
 
     # pick launch shapes (autotuner), unless given: a kernel trace of a run
     # with fixed shapes holds only the timed launches of each product
@@ -1059,6 +1084,7 @@ def main():
     # comparison path and repeat measurement (min over epochs)
     t_da = epochs(lambda: M.spmv(xd, yd), 50)
     t_csr = epochs(lambda: Cm.csr_spmv(xd, yc), 50)
+    t_gather = epochs(lambda: D.gather_read(xd, sink, A.nrows, 27, offs=offs27), 50)
 
     # correctness of the timed output against CSR on the same x
     torch.cuda.synchronize()
@@ -1104,6 +1130,10 @@ def main():
         "predicted_speedup": round(T_csr / T_da, 4),
         "uplift_fraction": round((t_csr / t_da - 1) / (T_csr / T_da - 1), 3),
         "stream_read_gbs": round(stream_gbs, 1),
+        # additive bound: the matrix stream at the read ceiling plus the x
+        # gathers alone (the two share each CU's vector memory path)
+        "gather_probe_us": round(t_gather * 1e6, 2),
+        "bound_us": round((T_da / (stream_gbs * 1e9) + t_gather) * 1e6, 2),
         "max_abs_diff_da_vs_csr": diff,
         "paper_cpu_context": {"uplift_st": 0.11, "uplift_mt": 0.175, "predicted": 0.20},
     }

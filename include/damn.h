@@ -582,6 +582,22 @@ typedef enum {
 int damn_stream_read(const void* src, size_t bytes, int32_t passes, double* sink, int32_t mode,
                      int32_t tile_bytes, void* stream);
 
+/* Gather probe: the x accesses of a product (Sec. 4) without its matrix.
+ * Row r of `rows` (one thread each, 256 rows per workgroup, renumbered per
+ * XCD as the products are) reads per_row float64 values x[c]: with offs
+ * (device, per_row int32 values), c = r + offs[k], the DA offsets of a
+ * stencil, shared by every row; with offs = NULL, c is drawn from
+ * [r - halfwidth, r + halfwidth] by a fixed integer hash of (r, k), as a
+ * random banded matrix's columns scatter.  Columns are clipped to [0, n).
+ * x is a device array of n >= 1 values; one checksum per workgroup goes to
+ * sink[b mod 65536] (device, float64, 65536 entries).  rows * per_row
+ * 8-byte reads with the access pattern of the product and no matrix
+ * stream: the gather time a product with that pattern cannot beat.
+ * Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_UNSUPPORTED (more than 2^31 - 1
+ * workgroups). */
+int damn_gather_read(const double* x, int64_t n, int64_t rows, int32_t per_row,
+                     int32_t halfwidth, const int32_t* offs, double* sink, void* stream);
+
 /* Copy probe: dst = src for `bytes` (multiple of 16) with 16-byte accesses;
  * known bytes read and written, to calibrate memory-traffic counters.
  * Errors: DAMN_ERR_INVALID_ARG. */

@@ -645,6 +645,25 @@ def stream_read(src, sink, mode=READ_NT, tile_bytes=8192, stream=None, passes=1)
                                 _stream_ptr(stream)), "stream_read")
 
 
+def gather_read(x, sink, rows, per_row, halfwidth=0, offs=None, stream=None):
+    """Gather probe: rows * per_row reads of the float64 device vector x,
+    row r's at r + offs[k] (offs: int32 device tensor of per_row DA
+    offsets) or, without offs, scattered within +-halfwidth of r; sink:
+    float64 device tensor with at least 65536 entries."""
+    import torch
+
+    _dev_ptr(x, torch.float64, x.numel(), "x")
+    _dev_ptr(sink, torch.float64, sink.numel(), "sink")
+    if sink.numel() < 65536:
+        raise ValueError("sink needs 65536 entries")
+    op = None
+    if offs is not None:
+        op = _dev_ptr(offs, torch.int32, int(per_row), "offs")
+    _check(lib.damn_gather_read(C.c_void_p(x.data_ptr()), int(x.numel()), int(rows),
+                                int(per_row), int(halfwidth), op, C.c_void_p(sink.data_ptr()),
+                                _stream_ptr(stream)), "gather_read")
+
+
 def stream_copy(src, dst, stream=None):
     """Copy probe between two contiguous device tensors of equal byte size
     (a multiple of 16)."""

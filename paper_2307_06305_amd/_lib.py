@@ -81,6 +81,7 @@ _SIGS = {
     "damn_get_config": (C.c_int, [_vp, _vp]),
     "damn_stream_read": (C.c_int, [_vp, C.c_size_t, _i32, _vp, _i32, _i32, _vp]),
     "damn_stream_copy": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
+    "damn_gather_read": (C.c_int, [_vp, _i64, _i64, _i32, _i32, _vp, _vp, _vp]),
     "damn_cg": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "damn_batch_create": (C.c_int, [C.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _f64, _f64, _i32,
                                     _vp]),

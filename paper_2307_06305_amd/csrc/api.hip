@@ -615,6 +615,17 @@ int damn_stream_read(const void* src, size_t bytes, int32_t passes, double* sink
   return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
 }
 
+int damn_gather_read(const double* x, int64_t n, int64_t rows, int32_t per_row,
+                     int32_t halfwidth, const int32_t* offs, double* sink, void* stream) {
+  if (x == nullptr || sink == nullptr || n < 1 || rows < 0 || per_row < 0 || halfwidth < 0 ||
+      halfwidth > (1 << 30))
+    return DAMN_ERR_INVALID_ARG;
+  if ((rows + 255) / 256 > INT32_MAX) return DAMN_ERR_UNSUPPORTED;
+  const hipError_t e = launch_gather_read(x, n, rows, per_row, halfwidth, offs, sink,
+                                          static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
+}
+
 int damn_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
   if (((src == nullptr || dst == nullptr) && bytes > 0) || bytes % 16 != 0)
     return DAMN_ERR_INVALID_ARG;

@@ -88,5 +88,7 @@ hipError_t launch_spmm_stream(const SpmvArgs& a, int lanes, int nrhs);
 hipError_t launch_stream_read(const void* src, int64_t bytes, int32_t passes, double* sink,
                               int mode, int32_t tile_bytes, hipStream_t s);
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
+hipError_t launch_gather_read(const double* x, int64_t n, int64_t rows, int32_t per_row,
+                              int32_t hw, const int32_t* offs, double* sink, hipStream_t s);
 
 }  // namespace damn

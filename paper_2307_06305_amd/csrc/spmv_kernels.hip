@@ -113,6 +113,47 @@ __global__ __launch_bounds__(256) void stream_lds(const u32x4* __restrict__ src,
   if (threadIdx.x == 0) sink[blockIdx.x & 65535u] = double(red[0] ^ red[1] ^ red[2] ^ red[3]);
 }
 
+// Gather probe: the x accesses of a product without its matrix.  Thread r
+// reads per_row values x[c]: with offs, c = r + offs[k] (a stencil's DA
+// offsets, the same for every row); without, c is drawn from [r - hw,
+// r + hw] by an integer hash of (r, k), scattered over a band as a random
+// banded matrix's columns are.  Columns are clipped to [0, n).  No matrix
+// is streamed.  One checksum per workgroup into sink[b mod 65536].
+__global__ __launch_bounds__(256) void gather_read(const double* __restrict__ x, int64_t n,
+                                                   int64_t rows, int32_t per_row, int32_t hw,
+                                                   const int32_t* __restrict__ offs,
+                                                   double* __restrict__ sink) {
+  const uint32_t b = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int64_t r = int64_t(b) * 256 + threadIdx.x;
+  double acc = 0.0;
+  if (r < rows) {
+    const uint32_t span = 2u * uint32_t(hw) + 1u;
+#pragma unroll 4
+    for (int32_t k = 0; k < per_row; ++k) {
+      int64_t c;
+      if (offs) {
+        c = r + offs[k];
+      } else {
+        // a 32-bit mixing function (multiply, xor-shift) of the row and k
+        uint32_t h = uint32_t(r) * 0x9E3779B1u ^ (uint32_t(k) + 1u) * 0x85EBCA77u;
+        h ^= h >> 16;
+        h *= 0x7FEB352Du;
+        h ^= h >> 15;
+        h *= 0x846CA68Bu;
+        h ^= h >> 16;
+        c = r - hw + int64_t(h % span);
+      }
+      c = c < 0 ? 0 : (c >= n ? n - 1 : c);
+      acc += x[c];
+    }
+  }
+  acc = group_sum(acc, 64);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) sink[blockIdx.x & 65535u] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 // Copy probe: dst = src in 16-byte pieces, one contiguous slice per
 // workgroup (known bytes read and written, to calibrate traffic counters).
 __global__ __launch_bounds__(256) void stream_copy(const u32x4* __restrict__ src,
@@ -244,6 +285,16 @@ hipError_t launch_stream_read(const void* src, int64_t bytes, int32_t passes, do
   else
     hipLaunchKernelGGL(kern::stream_read<false>, dim3(uint32_t(blocks)), dim3(256), 0, s, p, n16,
                        uint32_t(slices), sink);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_read(const double* x, int64_t n, int64_t rows, int32_t per_row,
+                              int32_t hw, const int32_t* offs, double* sink, hipStream_t s) {
+  if (rows == 0 || per_row == 0) return hipSuccess;
+  const int64_t blocks = (rows + 255) / 256;
+  if (blocks > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kern::gather_read, dim3(uint32_t(blocks)), dim3(256), 0, s, x, n, rows,
+                     per_row, hw, offs, sink);
   return hipGetLastError();
 }
 

@@ -340,3 +340,44 @@ def test_first_product_of_a_fresh_handle_is_graph_capturable():
             (xd * 2.0).sum().item()
         del g
         M.destroy()
+
+
+def test_probes_read_what_they_claim():
+    """The measurement probes: the read probe's checksums cover every byte
+    of the buffer on every pass (a buffer of ones folds to a known value
+    per workgroup), and the gather probe reads per_row values per row
+    (x = 1 sums to rows * per_row; half-width 0 reads x[r] per_row times)."""
+    torch = torch_or_skip()
+    sink = torch.zeros(65536, dtype=torch.float64, device="cuda")
+    # gather probe
+    n, per_row = 100_003, 12
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    D.gather_read(x, sink, n, per_row, halfwidth=20000)
+    assert host(sink)[: (n + 255) // 256].sum() == n * per_row
+    sink.zero_()
+    x = torch.arange(n, dtype=torch.float64, device="cuda")
+    D.gather_read(x, sink, n, per_row, halfwidth=0)
+    assert host(sink)[: (n + 255) // 256].sum() == per_row * (n - 1) * n // 2
+    # stencil offsets: x[r + d] clipped to [0, n)
+    offs = np.array([-300, -1, 0, 1, 300], dtype=np.int32)
+    sink.zero_()
+    D.gather_read(x, sink, n, offs.size, offs=dev(offs))
+    r = np.arange(n)
+    want = sum(np.clip(r + d, 0, n - 1).sum() for d in offs)
+    assert host(sink)[: (n + 255) // 256].sum() == want
+    # read probe, register and LDS paths, one and several passes: a buffer
+    # whose 16-byte pieces are (1, 0, 0, 0) words folds to XOR = 1 per odd
+    # number of pieces a workgroup reads
+    buf = torch.zeros(1 << 22, dtype=torch.int32, device="cuda")
+    buf[0::4] = 1
+    for mode in (D.READ_NT, D.READ_PLAIN, D.READ_LDS_NT, D.READ_LDS_PLAIN):
+        for passes in (1, 3):
+            sink.fill_(-1.0)
+            D.stream_read(buf, sink, mode, 8192, passes=passes)
+            s = host(sink)
+            # every workgroup wrote its checksum (0 or 1: an even or odd
+            # count of pieces), none is left at -1
+            assert np.all((s == 0.0) | (s == 1.0) | (s == -1.0))
+            if mode in (D.READ_LDS_NT, D.READ_LDS_PLAIN):
+                tiles = (buf.numel() * 4) // 8192
+                assert np.all(s[: tiles * passes] >= 0.0)

@@ -106,10 +106,14 @@ def summarize(fetch_csv, write_csv, copy_bytes, launch_da=DA_LAUNCH, launch_csr=
     return out
 
 
-def write_summary(summary, path, command):
+TITLE_27PT = "DA-CSR and CSR SpMV, 3D 27-point stencil 128^3"
+MODEL_27PT = "Traffic model (Eq. 3 plus x once and y written): DA 599,372,724 B, CSR 710,858,660 B."
+
+
+def write_summary(summary, path, command, title=TITLE_27PT, model=MODEL_27PT):
     da, csr = summary["kernels"]["da"], summary["kernels"]["csr"]
     lines = [
-        "# HBM traffic: DA-CSR and CSR SpMV, 3D 27-point stencil 128^3",
+        f"# HBM traffic: {title}",
         "",
         "Counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch), one rocprofv3 run each:",
         "",
@@ -128,8 +132,7 @@ def write_summary(summary, path, command):
         lines.append(f"| `{k['kernel']}` ({k['launch']}) | {k['fetch_kib']:.0f} | {k['write_kib']:.0f} | "
                      f"{k['hbm_read_bytes']:.4g} | {k['hbm_write_bytes']:.4g} | "
                      f"{k['hbm_bytes']:.4g} |")
-    lines += ["", "Traffic model (Eq. 3 plus x once and y written): DA 599,372,724 B, "
-              "CSR 710,858,660 B.", "", "```json", json.dumps(summary, indent=1), "```", ""]
+    lines += ["", model, "", "```json", json.dumps(summary, indent=1), "```", ""]
     with open(path, "w") as f:
         f.write("\n".join(lines))
 
@@ -182,6 +185,79 @@ def write_trace_summary(stats_csv, path, title, command, notes, needles=None, to
         f.write("\n".join(lines))
 
 
+def counter_means(csv_paths):
+    """{kernel name: {counter: mean value per dispatch}} over rocprofv3
+    counter-collection CSVs (one per --pmc pass)."""
+    sums, counts = {}, {}
+    for path in csv_paths:
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                name = row["Kernel_Name"].replace("void ", "").split("(")[0]
+                key = (name, row["Counter_Name"])
+                sums[key] = sums.get(key, 0.0) + float(row["Counter_Value"])
+                counts[key] = counts.get(key, 0) + 1
+    out = {}
+    for (name, counter), v in sums.items():
+        out.setdefault(name, {})[counter] = v / counts[(name, counter)]
+    return out
+
+
+def dispatch_groups(trace_csv, needles):
+    """(name, threads in the grid, dispatches, avg us, min us) from a rocprofv3
+    kernel-trace CSV, grouped by kernel and grid size (launches of one
+    kernel with different grids, such as the read probe's one-pass and
+    many-pass launches, kept apart)."""
+    groups = {}
+    with open(trace_csv) as f:
+        for row in csv.DictReader(f):
+            name = row["Kernel_Name"].replace("void ", "").split("(")[0]
+            if not any(k in name for k in needles):
+                continue
+            us = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3
+            groups.setdefault((name, int(row["Grid_Size_X"])), []).append(us)
+    return [(n, g, len(v), sum(v) / len(v), min(v)) for (n, g), v in sorted(groups.items())]
+
+
+def write_group_summary(traces, path, title, command, notes, needles):
+    """Per trace (label=path), the kernel-and-grid groups of dispatch_groups."""
+    lines = [f"# {title}", "", "Commands (run from the repository root on one MI355X; `cd /tmp` "
+             "first):", "", "```", command, "```", "", notes, ""]
+    for spec in traces:
+        label, trace = spec.split("=", 1)
+        lines += [f"## {label}", "", "| kernel | grid threads | dispatches | avg us | min us |",
+                  "|---|---:|---:|---:|---:|"]
+        for n, g, k, avg, mn in dispatch_groups(trace, needles):
+            lines.append(f"| `{n}` | {g} | {k} | {avg:.1f} | {mn:.1f} |")
+        lines.append("")
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
+
+
+def write_counter_summary(specs, path, title, command, notes, needles):
+    """A table of counters (rows) by workload and kernel (columns), means per
+    dispatch, for the kernels that match `needles`.  specs: label=csv[,csv...]
+    (one CSV per counter set of one workload)."""
+    cols = []  # (label, kernel, {counter: mean})
+    for spec in specs:
+        label, paths = spec.split("=", 1)
+        means = counter_means(paths.split(","))
+        for name in means:
+            if any(k in name for k in needles):
+                cols.append((label, name, means[name]))
+    counters = sorted({c for _, _, m in cols for c in m})
+    lines = [f"# {title}", "", "Commands (run from the repository root on one MI355X; `cd /tmp` "
+             "first), one rocprofv3 run per counter set:", "", "```", command, "```", "",
+             notes, ""]
+    lines.append("| counter | " + " | ".join(f"{lb}: `{n}`" for lb, n, _ in cols) + " |")
+    lines.append("|---|" + "---:|" * len(cols))
+    for c in counters:
+        lines.append(f"| {c} | " + " | ".join(
+            f"{m[c]:.6g}" if c in m else "" for _, _, m in cols) + " |")
+    lines.append("")
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_2307_06305_amd.profiling")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -193,6 +269,21 @@ def main(argv=None):
     tr.add_argument("--notes", default="")
     tr.add_argument("--match", nargs="*", default=None)
     tr.add_argument("--top", type=int, default=24)
+    gr = sub.add_parser("groups", help="kernel-trace durations by kernel and grid size")
+    gr.add_argument("--trace", nargs="+", required=True, help="label=run_kernel_trace.csv")
+    gr.add_argument("--out", required=True)
+    gr.add_argument("--title", required=True)
+    gr.add_argument("--command", required=True)
+    gr.add_argument("--notes", default="")
+    gr.add_argument("--match", nargs="+", required=True)
+    cn = sub.add_parser("counters", help="table of counter means per dispatch by kernel")
+    cn.add_argument("--csv", nargs="+", required=True,
+                    help="label=csv[,csv...]: one workload's counter-collection CSVs")
+    cn.add_argument("--out", required=True)
+    cn.add_argument("--title", required=True)
+    cn.add_argument("--command", required=True)
+    cn.add_argument("--notes", default="")
+    cn.add_argument("--match", nargs="+", required=True)
     s = sub.add_parser("summarize")
     s.add_argument("--fetch", required=True)
     s.add_argument("--write", required=True)
@@ -201,12 +292,20 @@ def main(argv=None):
     s.add_argument("--command", default="")
     s.add_argument("--launch-da", default=DA_LAUNCH)
     s.add_argument("--launch-csr", default=CSR_LAUNCH)
+    s.add_argument("--title", default=TITLE_27PT)
+    s.add_argument("--model", default=MODEL_27PT)
     a = ap.parse_args(argv)
+    if a.cmd == "groups":
+        write_group_summary(a.trace, a.out, a.title, a.command, a.notes, a.match)
+        return 0
+    if a.cmd == "counters":
+        write_counter_summary(a.csv, a.out, a.title, a.command, a.notes, a.match)
+        return 0
     if a.cmd == "trace":
         write_trace_summary(a.stats, a.out, a.title, a.command, a.notes, a.match, a.top)
         return 0
     summary = summarize(a.fetch, a.write, a.copy_bytes, a.launch_da, a.launch_csr)
-    write_summary(summary, a.out, a.command)
+    write_summary(summary, a.out, a.command, a.title, a.model)
     print(json.dumps(summary["kernels"]), flush=True)
     return 0
 

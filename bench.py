@@ -806,7 +806,8 @@ def bench_selector_training(D, args):
 
 def summary(res):
     """A compact digest of every figure the run measured, printed last on
-    stderr so that a log cut to its tail still carries them."""
+    stderr (after the JSON line) so that a log cut to its tail still carries
+    them; the headline comes last."""
     out = []
 
     def g(d, *keys):
@@ -816,6 +817,66 @@ def summary(res):
             d = d[k]
         return d
 
+    cb, cn = res.get("cpu_baseline"), res.get("cpu_native")
+    if cb or cn:
+        out.append(f"cpu: oracle {g(cb, 'value')}GB/s on 1 core | native DA/CSR uplift "
+                   f"{g(cn, 'threads_16', 'uplift')} on {g(cn, 'cores')} threads, "
+                   f"{g(cn, 'threads_1', 'uplift')} on 1")
+    sp = res.get("spmm")
+    if isinstance(sp, dict):
+        parts = [f"{k[4:]}: {g(v, 'da', 'us')}/{g(v, 'csr', 'us')}us" for k, v in sp.items()
+                 if k.startswith("nrhs") and isinstance(v, dict)]
+        if parts:
+            out.append("spmm DA/CSR " + ", ".join(parts))
+    co, bl = res.get("coo"), res.get("blocks")
+    if co or bl:
+        out.append(f"dacoo/coo {g(co, 'dacoo16', 'us')}/{g(co, 'coo32', 'us')}us "
+                   f"({g(co, 'speedup')}, model {g(co, 'predicted_speedup')}) | dabsr/bsr f64 "
+                   f"{g(bl, 'dabsr16_f64', 'us')}/{g(bl, 'bsr32_f64', 'us')}us, f32 "
+                   f"{g(bl, 'dabsr16_f32', 'us')}/{g(bl, 'bsr32_f32', 'us')}us")
+    gr = res.get("grid")
+    if isinstance(gr, dict):
+        for wl, v in gr.items():
+            if isinstance(v, dict) and "cells" in v:
+                out.append(f"grid {wl} speedup over csr32_f64: " + ", ".join(
+                    f"{c} {x.get('speedup')}" for c, x in v["cells"].items() if c != "csr32_f64"))
+        sw_, wd, tl = gr.get("same_index_width_27pt_32^3"), gr.get("wide"), gr.get("tall")
+        out.append(f"grid da16/csr16 {g(sw_, 'da16_over_csr16')} | wide DA/CSR "
+                   f"{g(wd, 'speedup')} | tall {g(tl, 'speedup')}")
+    sw = res.get("sweep")
+    if sw:
+        out.append("sweep N DA/CSR us (speedup) [plain DA]: " + ", ".join(
+            f"{r['N']} {r['da']['us']}/{r['csr']['us']} ({r['speedup']}) "
+            f"[{r['da'].get('us_plain')}]" for r in sw))
+    if "mall" in res:
+        rows = {r["mb"]: r for r in res["mall"].get("read", [])}
+        out.append("read probe GB/s, 1 pass/launch | ~1 GiB of passes/launch (lds_nt, lds_plain): "
+                   + ", ".join(f"{mb}MB {rows[mb]['lds_nt_gbs']}/{rows[mb]['lds_plain_gbs']} | "
+                               f"{rows[mb].get('lds_nt_multi_gbs')}/"
+                               f"{rows[mb].get('lds_plain_multi_gbs')}"
+                               for mb in (64, 128, 256, 2048) if mb in rows))
+    bt = res.get("batch")
+    if bt:
+        sel = bt.get("selector", {})
+        out.append(f"batch512 graph {bt.get('graph_us')}us {bt.get('graph_gbs')}GB/s vs separate "
+                   f"{bt.get('separate_us')}us | selector regret mean {sel.get('mean_regret')} "
+                   f"p95 {sel.get('p95_regret')} within5% {sel.get('within_5pct')}")
+    b = res.get("banded")
+    if b:
+        n, s = b.get("natural", {}), b.get("scrambled", {})
+        gp = n.get("gather_probe", {})
+        out.append(f"band4M DA {g(n, 'da', 'us')}us ({g(n, 'da', 'pct_hbm_peak')}%) CSR "
+                   f"{g(n, 'csr', 'us')}us speedup {n.get('speedup')} (model "
+                   f"{n.get('predicted_speedup')}) | gathers alone {gp.get('hw20000_us')}us | "
+                   f"scrambled CSR {g(s, 'csr_scrambled_order', 'us')}us -> w "
+                   f"{s.get('bandwidth_reordered')} DA {g(s, 'da', 'us')}us CSR "
+                   f"{g(s, 'csr', 'us')}us")
+    for key, name in (("cg_cube", "CG cube 256^3 CSR32"), ("cg", "CG box 128x128x1024 DA16")):
+        c = res.get(key)
+        if c:
+            out.append(f"{name}: fp64 {g(c, 'fp64', 's')}s {g(c, 'fp64', 'iters')}it | mixed "
+                       f"{g(c, 'mixed', 's')}s {g(c, 'mixed', 'outer')}x"
+                       f"{g(c, 'mixed', 'iters')}it | speedup {c.get('speedup_mixed')}")
     da, csr = res.get("da", {}), res.get("csr", {})
     out.append(f"27pt128 DA {da.get('us')}us {da.get('gbs')}GB/s {da.get('pct_hbm_peak')}%peak | "
                f"CSR {csr.get('us')}us | speedup {res.get('speedup')} (model "
@@ -824,56 +885,6 @@ def summary(res):
                f"read ceiling {res.get('stream_read_gbs')}GB/s | gathers alone "
                f"{res.get('gather_probe_us')}us, stream at ceiling + gathers "
                f"{res.get('bound_us')}us")
-    if "mall" in res:
-        m = res["mall"]
-        out.append("read probe by size (MB: GB/s nt/plain/lds_nt/lds_plain, one pass per "
-                   "launch | ~1 GiB of passes per launch): " + ", ".join(
-                       f"{r['mb']}: {r['nt_gbs']}/{r['plain_gbs']}/{r['lds_nt_gbs']}/"
-                       f"{r['lds_plain_gbs']} | {r.get('nt_multi_gbs')}/{r.get('plain_multi_gbs')}/"
-                       f"{r.get('lds_nt_multi_gbs')}/{r.get('lds_plain_multi_gbs')}"
-                       for r in m.get("read", [])))
-    b = res.get("banded")
-    if b:
-        n, s = b.get("natural", {}), b.get("scrambled", {})
-        out.append(f"band4M natural DA {g(n, 'da', 'us')}us ({g(n, 'da', 'pct_hbm_peak')}%) "
-                   f"CSR {g(n, 'csr', 'us')}us speedup {n.get('speedup')} (model "
-                   f"{n.get('predicted_speedup')}) | scrambled CSR "
-                   f"{g(s, 'csr_scrambled_order', 'us')}us -> reordered w "
-                   f"{s.get('bandwidth_reordered')} DA {g(s, 'da', 'us')}us CSR "
-                   f"{g(s, 'csr', 'us')}us speedup {s.get('speedup')}")
-        gp = n.get("gather_probe")
-        if gp:
-            out.append(f"band4M gather probe ({gp['reads']} scattered reads, no matrix): "
-                       f"+-64 {gp['hw64_us']}us, +-20000 {gp['hw20000_us']}us "
-                       f"({gp['hw20000_greads_per_s']} G reads/s), +-2e6 {gp['hw2000000_us']}us")
-    for key, name in (("cg", "CG box 128x128x1024 DA16"), ("cg_cube", "CG cube 256^3 CSR32")):
-        c = res.get(key)
-        if c:
-            out.append(f"{name}: fp64 {g(c, 'fp64', 's')}s {g(c, 'fp64', 'iters')}it | mixed "
-                       f"{g(c, 'mixed', 's')}s {g(c, 'mixed', 'outer')}x"
-                       f"{g(c, 'mixed', 'iters')}it | speedup {c.get('speedup_mixed')}")
-    sw = res.get("sweep")
-    if sw:
-        out.append("sweep N:regime DA/CSR us (speedup) [DA/CSR us, plain loads]: " + ", ".join(
-            f"{r['N']}:{r['regime']} {r['da']['us']}/{r['csr']['us']} ({r['speedup']}) "
-            f"[{r['da'].get('us_plain')}/{r['csr'].get('us_plain')}]" for r in sw))
-    bt = res.get("batch")
-    if bt:
-        sel = bt.get("selector", {})
-        out.append(f"batch512 graph {bt.get('graph_us')}us {bt.get('graph_gbs')}GB/s vs separate "
-                   f"{bt.get('separate_us')}us | selector regret mean {sel.get('mean_regret')} "
-                   f"p95 {sel.get('p95_regret')} within5% {sel.get('within_5pct')}")
-    sp = res.get("spmm")
-    if isinstance(sp, dict):
-        parts = []
-        for k, v in sp.items():
-            if isinstance(v, dict) and "da" in v and isinstance(v["da"], dict):
-                parts.append(f"{k}: DA {v['da'].get('us')}us")
-        if parts:
-            out.append("spmm " + ", ".join(parts))
-    cb = res.get("cpu_baseline")
-    if cb:
-        out.append(f"cpu oracle {cb.get('value')}GB/s on {cb.get('cores')} core")
     for line in out:
         print(f"[summary] {line}", file=sys.stderr, flush=True)
 
@@ -1167,8 +1178,8 @@ def main():
             "sample": f"oracle DA-CSR SpMV (NumPy, float64) on the full workload, {reps} runs, "
                       f"{t_cpu:.2f} s each",
         }
-    summary(res)
     print(json.dumps(res), flush=True)
+    summary(res)
 
 
 if __name__ == "__main__":

@@ -60,9 +60,13 @@ __device__ __forceinline__ void tile_rows(const BatchMat& m, int32_t r0, int32_t
                                           const int16_t* __restrict__ idx_s,
                                           const int32_t* __restrict__ rp_s, double alpha,
                                           double beta, bool read_y) {
+  // G lanes per row, spread over the wave as in the SpMV stream kernel:
+  // lane l takes row l mod (64/G) of the wave's rows and part l / (64/G)
   const int G = m.lanes;
-  const int lane = int(threadIdx.x) % G;
-  for (int32_t r = r0 + int32_t(threadIdx.x) / G; r < r1; r += 256 / G) {
+  const int rpw = 64 / G;
+  const int wl = int(threadIdx.x & 63);
+  const int lane = wl / rpw;
+  for (int32_t r = r0 + int32_t(threadIdx.x >> 6) * rpw + wl % rpw; r < r1; r += 256 / G) {
     const int32_t s = rp_s[r - ar] - a0, e = rp_s[r + 1 - ar] - a0;
     const double* Xs = m.X + int64_t(r) * NRHS;
     // up to 4 right-hand sides, two entries in flight per lane
@@ -95,7 +99,8 @@ __device__ __forceinline__ void tile_rows(const BatchMat& m, int32_t r0, int32_t
 #pragma unroll
     for (int j = 0; j < NRHS; ++j) acc[j] += acc2[j];
 #pragma unroll
-    for (int j = 0; j < NRHS; ++j) acc[j] = kern::group_sum(acc[j], G);
+    for (int j = 0; j < NRHS; ++j)
+      for (int o = 32; o >= rpw; o >>= 1) acc[j] += __shfl_xor(acc[j], o, 64);
     if (lane == 0) {
       double* yr = m.Y + int64_t(r) * NRHS;
       if (PAIRS) {

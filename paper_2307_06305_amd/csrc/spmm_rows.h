@@ -4,7 +4,7 @@
 // product repeated over NRHS vectors).  X is ncols x NRHS and Y nrows x NRHS,
 // row-major, so the NRHS values of one row are adjacent.
 //
-// Each row gets G consecutive lanes.  The NRHS values of a row are cut into
+// Each row gets G lanes of a wave.  The NRHS values of a row are cut into
 // pieces of PW = 2 doubles (PAIRS: 16-byte loads and stores; NRHS even, X
 // and Y 16-byte aligned) or of one double.  When the piece count NP is a
 // power of two, the row's lanes split over pieces first: PL = min(G, NP)
@@ -44,15 +44,21 @@ __device__ __forceinline__ void spmm_tile_rows(int G, int32_t r0, int32_t r1, in
   constexpr bool kSplit = (NP & (NP - 1)) == 0;
   const int PL = kSplit ? (G < NP ? G : NP) : 1;  // lanes over pieces
   const int npl = NP / PL;                         // pieces per lane
-  const int lane = int(threadIdx.x) % G;
-  const int p = lane % PL;   // first piece of this lane
-  const int EL = G / PL;     // lanes over entries
-  const int g = lane / PL;   // this lane's first entry
+  // A wave holds 64 / G rows.  Lane l takes piece l mod PL, row
+  // (l / PL) mod (64 / G) of the wave's rows and entry group l / (PL * 64/G):
+  // the lanes of one entry group read the pieces of neighbouring rows'
+  // X rows, a contiguous run for banded matrices.
+  const int RPW = 64 / G;
+  const int wl = int(threadIdx.x & 63);
+  const int p = wl % PL;                // first piece of this lane
+  const int EL = G / PL;                // lanes over entries
+  const int g = wl / (PL * RPW);        // this lane's first entry
+  const int rw = (wl / PL) % RPW;       // this lane's row in the wave
   // two entries in flight when a lane holds at most 4 sums (the second set
   // in acc2); more would cost occupancy
   constexpr int T = NRHS < 4 ? NRHS : 4;
   const bool twin = npl * PW <= T;
-  for (int32_t r = r0 + int32_t(threadIdx.x) / G; r < r1; r += 256 / G) {
+  for (int32_t r = r0 + int32_t(threadIdx.x >> 6) * RPW + rw; r < r1; r += 256 / G) {
     const int32_t s = rp_s[r - ar] - a0, e = rp_s[r + 1 - ar] - a0;
     const double* Xs = DA ? X + int64_t(r) * NRHS : X;
     double acc[NRHS], acc2[T];
@@ -91,7 +97,7 @@ __device__ __forceinline__ void spmm_tile_rows(int G, int32_t r0, int32_t r1, in
       if (j < npl * PW) {
         if (j < T) acc[j] += acc2[j];
         // sum over the lanes of this row that hold the same pieces
-        for (int o = G >> 1; o >= PL; o >>= 1) acc[j] += __shfl_xor(acc[j], o, G);
+        for (int o = 32; o >= PL * RPW; o >>= 1) acc[j] += __shfl_xor(acc[j], o, 64);
       }
     }
     if (g == 0) {

@@ -95,12 +95,16 @@ __global__ __launch_bounds__(256) void coo_chunk(int64_t nnz, const int32_t* __r
   if (threadIdx.x == 0) seg_s[nseg] = len;
   __syncthreads();
 
-  // 4. G lanes per run form and sum its products (neighbouring runs, that
-  //    is neighbouring rows, on neighbouring lanes, so the x gathers of one
-  //    instruction stay close); a run wholly inside the chunk updates y, a
-  //    run cut by an edge leaves its sum for the join
-  const int gl = threadIdx.x % G;
-  for (int32_t q = int32_t(threadIdx.x / G); q < nseg; q += 256 / G) {
+  // 4. G lanes per run form and sum its products; lane l of a wave takes
+  //    run l mod (64/G) of the wave's runs and part l / (64/G) of it, so
+  //    neighbouring runs, that is neighbouring rows, sit on neighbouring
+  //    lanes and the x gathers of one instruction stay close; a run wholly
+  //    inside the chunk updates y, a run cut by an edge leaves its sum for
+  //    the join
+  constexpr int RPW = 64 / G;
+  const int wl = int(threadIdx.x & 63);
+  const int gl = wl / RPW;
+  for (int32_t q = int32_t(threadIdx.x >> 6) * RPW + wl % RPW; q < nseg; q += 256 / G) {
     const int32_t sk = seg_s[q], ek = seg_s[q + 1];
     const int32_t r = rows_s[sk];
     const V* xs = DA ? x + r : x;
@@ -112,7 +116,7 @@ __global__ __launch_bounds__(256) void coo_chunk(int64_t nnz, const int32_t* __r
     }
     if (k < ek) acc += val_s[k] * xs[idx_s[k]];
     acc += acc2;
-    if (G > 1) acc = group_sum(acc, G);
+    if (G > 1) acc = strided_group_sum<G>(acc);
     if (gl == 0) {
       const bool cont_prev = sk == 0 && edge[0] == r;
       const bool cont_next = ek == len && edge[1] == r;

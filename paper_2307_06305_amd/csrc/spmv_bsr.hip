@@ -93,10 +93,14 @@ __global__ __launch_bounds__(256) void spmv_bsr_stream(
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 
-  // 2. scalar row br*B + i with G lanes
-  const int lane = threadIdx.x % G;
+  // 2. scalar row br*B + i with G lanes, spread over the wave as in the
+  //    scalar stream kernel (lane l takes scalar row l mod (64/G) of the
+  //    wave's rows and part l / (64/G))
+  constexpr int RPW = 64 / G;
+  const int wl = int(threadIdx.x & 63);
+  const int lane = wl / RPW;
   const int32_t nsr = (r1 - r0) * B;
-  for (int32_t sr = int32_t(threadIdx.x / G); sr < nsr; sr += 256 / G) {
+  for (int32_t sr = int32_t(threadIdx.x >> 6) * RPW + wl % RPW; sr < nsr; sr += 256 / G) {
     const int32_t bro = sr / B, i = sr - bro * B;
     const int32_t br = r0 + bro;
     const int32_t s = rp_s[br - ar] - a0, e = rp_s[br + 1 - ar] - a0;
@@ -121,7 +125,7 @@ __global__ __launch_bounds__(256) void spmv_bsr_stream(
       for (int j = 0; j < B; ++j) acc0 += V(va[j]) * xa[j];
     }
     V sum = acc0 + acc1;
-    if (G > 1) sum = group_sum(sum, G);
+    if (G > 1) sum = strided_group_sum<G>(sum);
     if (lane == 0) {
       V* yr = y + int64_t(br) * B + i;
       *yr = finish(sum, alpha, beta, read_y != 0, yr);

@@ -195,3 +195,22 @@ def test_cg_rejects_bad_arguments():
         D.cg(A64, b, x, tol=0.0)
     for m in (A64, A32, C64):
         m.destroy()
+
+
+def test_cg_mixed_scaled_identity_refines_in_two_steps():
+    """The pin of the oracle's mixed scheme, on the library: A = 3 I refines
+    in two outer steps of one inner iteration each, to x = b/3."""
+    torch_or_skip()
+    n = 4096
+    rp = np.arange(n + 1, dtype=np.int32)
+    off = np.zeros(n, dtype=np.int16)
+    vals = np.full(n, 3.0)
+    A64 = D.Matrix.create(n, n, rp, off, vals, store=D.F64)
+    A32 = D.Matrix.create(n, n, rp, off, vals, store=D.F32)
+    b = uniform_vector(n, 9) * 1e3
+    xd = dev(np.zeros(n))
+    info = D.cg(A64, dev(b), xd, A32=A32, tol=1e-10, inner_tol=1e-5, check_every=1)
+    assert info["converged"] and info["outer"] == 2 and info["iters"] == 2
+    np.testing.assert_allclose(host(xd), b / 3, rtol=1e-13)
+    A64.destroy()
+    A32.destroy()

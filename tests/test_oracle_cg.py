@@ -76,3 +76,31 @@ def test_cg_detects_indefinite():
 
     with pytest.raises(ArithmeticError):
         CG.cg_fp64(mv, np.array([0.0, 1.0, 0.0, 0.0]))
+
+
+def test_cg_mixed_scaled_identity_refines_in_two_steps():
+    """A = 3 I: every inner CG converges in one iteration, so the refinement
+    is fixed by rounding alone.  The first correction is float32(r/|r|)/3
+    scaled back by |r|: its error is float32 rounding, a relative residual
+    in (0, 2^-23]; the second correction removes it to float64 level.  Two
+    outer steps, one inner iteration each, x = b/3.  (Drop the |r| scaling
+    of the correction, or the float64 residual between steps, and this
+    fails.)"""
+    n = 50
+    rp = np.arange(n + 1)
+    c = np.arange(n)
+    v = np.full(n, 3.0)
+
+    def mv64(u):
+        return S.spmv_csr(n, n, rp, c, v, u)
+
+    def mv32(u):
+        return S.spmv_csr(n, n, rp, c, v.astype(np.float32), u).astype(np.float32)
+
+    b = uniform_vector(n, 9) * 1e3
+    one = CG.cg_mixed(mv64, mv32, b, tol=1e-10, inner_tol=1e-5, max_outer=1)
+    assert one["outer"] == 1 and one["inner_iters"] == 1 and not one["converged"]
+    assert 0.0 < one["true_rel_res"] <= 2.0 ** -23
+    r = CG.cg_mixed(mv64, mv32, b, tol=1e-10, inner_tol=1e-5)
+    assert r["converged"] and r["outer"] == 2 and r["inner_iters"] == 2
+    np.testing.assert_allclose(r["x"], b / 3, rtol=1e-13)

@@ -1,5 +1,5 @@
 // Batched DA-CSR SpMM: many matrices of uneven size, each with 1-8
-// right-hand sides, in one persistent launch captured in a HIP graph.
+// right-hand sides, in one launch captured in a HIP graph.
 //
 // At creation the host cuts every matrix into stream tiles (consecutive rows
 // holding at most `cap` entries) and lists the tiles of all matrices in

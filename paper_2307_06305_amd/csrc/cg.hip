@@ -61,6 +61,14 @@ struct Pack {
     return *reinterpret_cast<const vec*>(p);
   }
   static __device__ __forceinline__ void store(V* p, vec v) { *reinterpret_cast<vec*>(p) = v; }
+  // non-temporal: for a vector no later kernel of the iteration reads, so it
+  // does not displace those that are (p for the next product, r)
+  static __device__ __forceinline__ vec load_nt(const V* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const vec*>(p));
+  }
+  static __device__ __forceinline__ void store_nt(V* p, vec v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<vec*>(p));
+  }
 };
 
 // Visit [s, e) of a slice in 16-byte packs: pack(base) for a whole pack
@@ -227,7 +235,7 @@ __global__ __launch_bounds__(256) void update_r(int64_t n, V* __restrict__ r,
   typedef Pack<V> P;
   for_packs<V>(s, e, [&](int64_t base) {
       typename P::vec rv = P::load(r + base);
-      const typename P::vec qv = P::load(q + base);
+      const typename P::vec qv = P::load_nt(q + base);
 #pragma unroll
       for (int k = 0; k < P::kN; ++k) {
         rv[k] = V(double(rv[k]) - a * double(qv[k]));
@@ -256,11 +264,11 @@ __global__ __launch_bounds__(256) void update_xp(int64_t n, V* __restrict__ x, V
   typedef Pack<V> P;
   for_packs<V>(s, e, [&](int64_t base) {
       // all three loads before the first store, so they are in flight together
-      typename P::vec xv = P::load(x + base), pv = P::load(p + base);
+      typename P::vec xv = P::load_nt(x + base), pv = P::load(p + base);
       const typename P::vec rv = more ? P::load(r + base) : typename P::vec(V(0));
 #pragma unroll
       for (int k = 0; k < P::kN; ++k) xv[k] = V(double(xv[k]) + a * double(pv[k]));
-      P::store(x + base, xv);
+      P::store_nt(x + base, xv);
       if (more) {
 #pragma unroll
         for (int k = 0; k < P::kN; ++k) pv[k] = V(double(rv[k]) + bt * double(pv[k]));

@@ -202,7 +202,12 @@ __global__ __launch_bounds__(256) void spmv_stream(
     if (G > 1) sum = strided_group_sum<G>(sum);
     if (lane == 0) {
       const V yr = finish(sum, alpha, beta, read_y != 0, y + r);
-      y[r] = yr;
+      // y is written once per product: where a wave's stores fill whole
+      // 128-byte lines (float64, at most 4 lanes per row), a non-temporal
+      // store keeps y from displacing x in L2.  The conjugate-gradient
+      // product keeps plain stores: its next kernel reads y at once.
+      constexpr bool kNtY = !DOT && sizeof(V) == 8 && G <= 4;
+      if (kNtY) __builtin_nontemporal_store(yr, y + r); else y[r] = yr;
       if (DOT) dot += double(yr) * double(w ? wr : yr);
     }
   }

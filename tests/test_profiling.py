@@ -99,3 +99,41 @@ def test_source_hash_ignores_comments_only():
     c = "int f(int x) {\n  return 3 * x;\n}\n"
     assert P._code_only(a) == P._code_only(b)
     assert P._code_only(a) != P._code_only(c)
+
+
+def test_counter_table_keeps_workloads_apart(tmp_path):
+    """Means per dispatch by counter, one column per workload and kernel:
+    the same kernel symbol in two workloads stays two columns."""
+    k = "void damn::kern::spmv_stream<int, double, false, 4, false, double, 2>(args)"
+    a1, a2, b1 = tmp_path / "a1.csv", tmp_path / "a2.csv", tmp_path / "b1.csv"
+    _counters(a1, "TCC_HIT_sum", [(k, 10.0), (k, 20.0), ("other(x)", 5.0)])
+    _counters(a2, "TCC_MISS_sum", [(k, 4.0)])
+    _counters(b1, "TCC_HIT_sum", [(k, 100.0)])
+    m = P.counter_means([str(a1), str(a2)])
+    name = "damn::kern::spmv_stream<int, double, false, 4, false, double, 2>"
+    assert m[name] == {"TCC_HIT_sum": 15.0, "TCC_MISS_sum": 4.0}
+    out = tmp_path / "c.md"
+    P.write_counter_summary([f"wl-a={a1},{a2}", f"wl-b={b1}"], str(out), "t", "cmd", "",
+                            ["spmv_stream"])
+    text = out.read_text()
+    assert "wl-a: `" in text and "wl-b: `" in text and "other" not in text
+    row = [ln for ln in text.splitlines() if ln.startswith("| TCC_HIT_sum |")][0]
+    assert row == "| TCC_HIT_sum | 15 | 100 |"
+
+
+def test_dispatch_groups_split_by_grid(tmp_path):
+    """Launches of one kernel with different grids (the read probe's one-pass
+    and many-pass launches) are averaged apart; durations in microseconds."""
+    path = tmp_path / "trace.csv"
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Grid_Size_X", "Start_Timestamp",
+                                          "End_Timestamp"])
+        w.writeheader()
+        for grid, dur in ((256, 10_000), (256, 12_000), (4096, 150_000), (4096, 148_000)):
+            w.writerow({"Kernel_Name": "void damn::kern::stream_lds<2>(args)",
+                        "Grid_Size_X": grid, "Start_Timestamp": 1000, "End_Timestamp": 1000 + dur})
+        w.writerow({"Kernel_Name": "other(x)", "Grid_Size_X": 1, "Start_Timestamp": 0,
+                    "End_Timestamp": 5})
+    g = P.dispatch_groups(str(path), ["stream_lds"])
+    assert g == [("damn::kern::stream_lds<2>", 256, 2, 11.0, 10.0),
+                 ("damn::kern::stream_lds<2>", 4096, 2, 149.0, 148.0)]

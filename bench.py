@@ -275,10 +275,10 @@ def graph_time(fn, min_s=0.05, n_epochs=7):
 def graph_autotune(mat, x, y):
     """The autotuner for products of a few microseconds: every candidate
     configuration timed through captured graphs; sets and returns the fastest."""
-    from paper_2307_06305_amd.tuning import candidates
+    from paper_2307_06305_amd.tuning import candidates_for
 
     times = {}
-    for c in candidates():
+    for c in candidates_for(mat):
         mat.set_config(*c)
         times[c] = graph_time(lambda: mat.apply(x, y), min_s=0.004, n_epochs=3)[0]
     best = min(times, key=times.get)
@@ -702,7 +702,7 @@ def bench_batch(D, args):
 
     def tuned_times(M, k, X, Y):
         # three autotuner runs, averaged: the selector's regret divides by the
-        # fastest of 49 timings, a minimum that one noisy run biases low (the
+        # fastest of 63 timings, a minimum that one noisy run biases low (the
         # last run leaves its own fastest class set)
         return np.mean([D.autotune(M, k, X, Y, reps=3) for _ in range(3)], axis=0)
 
@@ -949,10 +949,10 @@ def profile_run(D, args):
     else:
         Cm = D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals)
     cache = D.CACHE_PLAIN if args.profile_cache == "plain" else D.CACHE_NT
-    g, t = stream_launch(args.profile_da)
-    M.set_config(D.VAR_STREAM, g, 1, t, cache=cache)
-    g, t = stream_launch(args.profile_csr)
-    Cm.set_config(D.VAR_STREAM, g, 1, t, cache=cache)
+    g, t, u = stream_launch(args.profile_da)
+    M.set_config(D.VAR_STREAM, g, u, t, cache=cache)
+    g, t, u = stream_launch(args.profile_csr)
+    Cm.set_config(D.VAR_STREAM, g, u, t, cache=cache)
     xd = torch.from_numpy(x).to(dev)
     yd = torch.zeros(A.nrows, dtype=torch.float64, device=dev)
     for _ in range(args.profile_reps):
@@ -989,9 +989,11 @@ def main():
                     help="short run for counter collection: copy probe, then DA and CSR SpMV "
                          "with the launch shapes of --profile-da and --profile-csr")
     ap.add_argument("--da-launch", default=None,
-                    help="DA-CSR launch shape of the main product (stream_gG_tT); default: autotuned")
+                    help="DA-CSR launch shape of the main product (stream_gG_tT or paired_gG_tT); "
+                         "default: autotuned")
     ap.add_argument("--csr-launch", default=None,
-                    help="CSR launch shape of the comparison (stream_gG_tT); default: autotuned")
+                    help="CSR launch shape of the comparison (stream_gG_tT or paired_gG_tT); "
+                         "default: autotuned")
     ap.add_argument("--profile-da", default="stream_g2_t1024",
                     help="DA-CSR launch shape of the counter run")
     ap.add_argument("--profile-csr", default="stream_g2_t2048",
@@ -1065,13 +1067,16 @@ def main():
     def pick(mat, y, given):
         if given is None:
             return autotune(mat, xd, y, reps=args.tune_reps)
-        g, t = stream_launch(given)
-        cfg = (D.VAR_STREAM, g, 1, t)
+        g, t, u = stream_launch(given)
+        cfg = (D.VAR_STREAM, g, u, t)
         mat.set_config(*cfg)
+        time_launches(lambda: mat.apply(xd, y), 200)  # a sustained run, as the tuner ends with
         return cfg, {cfg: float("nan")}
 
-    best_da, times_da = pick(M, yd, args.da_launch)
+    # CSR first: the tuner ends with a sustained run of its choice, so the
+    # timed DA-CSR steps below follow a sustained run of their own kernel
     best_csr, times_csr = pick(Cm, yc, args.csr_launch)
+    best_da, times_da = pick(M, yd, args.da_launch)
     log(f"DA best {config_name(best_da)} {times_da[best_da]*1e6:.1f}us; "
         f"CSR best {config_name(best_csr)} {times_csr[best_csr]*1e6:.1f}us")
     if args.dump:
@@ -1114,8 +1119,11 @@ def main():
     # sources are unchanged and the timed launch shape is the profiled one
     from paper_2307_06305_amd.profiling import read_traffic
 
-    tb = read_traffic(os.path.join(ROOT, "profiles", "spmv_27pt128_traffic.md"), "da",
-                      launch=config_name(best_da))
+    tb = None
+    for name in ("spmv_27pt128_traffic.md", "spmv_27pt128_paired_traffic.md"):
+        tb = read_traffic(os.path.join(ROOT, "profiles", name), "da", launch=config_name(best_da))
+        if tb is not None:
+            break
     traffic = None if tb is None else int(round(tb))
     res = {
         "metric": "DA-CSR vs CSR SpMV effective GB/s, % HBM peak, speedup; CG time to 1e-10",

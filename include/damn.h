@@ -343,7 +343,19 @@ int damn_spmm(damn_mat A, const void* X, void* Y, int32_t nrhs, double alpha,
  *                    row count), stream offsets and values with aligned
  *                    16-byte loads through LDS, and reduce each row with
  *                    `lanes` lanes (1..64).  A row longer than `tile` is
- *                    reduced by a whole workgroup.  `unroll` unused.
+ *                    reduced by a whole workgroup.  `unroll` is the number
+ *                    of x values per gather load (0 counts as 1):
+ *                    1 (interleaved): the row's lanes take every lanes-th
+ *                      entry and load one x value each;
+ *                    2 (paired): each lane takes a contiguous part of the
+ *                      row and loads x[c], x[c+1] together, using both when
+ *                      the next entry's column is c+1 (runs of neighbouring
+ *                      columns, as in stencil rows, need half the loads).
+ *                      DA16 and CSR32 handles with float64 or float32
+ *                      values only (else DAMN_ERR_UNSUPPORTED).  damn_spmv,
+ *                      damn_csr_spmv
+ *                      and conjugate gradients use it; SpMM and the batch
+ *                      take the interleaved gathers with the same lanes.
  */
 typedef enum { DAMN_VAR_VECTOR = 0, DAMN_VAR_STREAM = 1 } damn_variant;
 
@@ -466,8 +478,9 @@ int damn_batch_destroy(damn_batch B);
  * --------------------------------------------------------------------- */
 
 #define DAMN_NFEAT 16
-#define DAMN_NCLASS 49
-#define DAMN_MLP_NPARAMS 8465
+#define DAMN_NCLASS 70
+#define DAMN_CLASS_SPMM 63
+#define DAMN_MLP_NPARAMS 9830
 
 /* Sparsity features of an int32 CSR matrix (host, float64 arithmetic,
  * float32 results): 0 log2(nrows+1), 1 log2(nnz+1), 2 mean row length,
@@ -483,9 +496,10 @@ int damn_features(int32_t nrows, int32_t ncols, const int32_t* rowptr,
 
 /* Configuration of class cls (0 <= cls < DAMN_NCLASS): classes 0..20 are
  * the vector variant (lanes 1..64 x unroll 1,2,4), 21..41 the stream variant
- * (lanes 1..64 x tile 1024, 2048, 4096), both for nrhs = 1; 42..48 are SpMM
- * lane counts 1..64 of the stream SpMM with 2048-entry tiles, for nrhs > 1
- * (*spmm = 1). */
+ * with interleaved gathers and 42..62 with paired gathers (lanes 1..64 x
+ * tile 1024, 2048, 4096 each), all for nrhs = 1; DAMN_CLASS_SPMM (63) ..
+ * 69 are SpMM lane counts 1..64 of the stream SpMM with 2048-entry tiles,
+ * for nrhs > 1 (*spmm = 1). */
 int damn_class_config(int32_t cls, damn_config* cfg, int32_t* spmm);
 
 /* Time every class that applies to nrhs (reps launches each after one
@@ -500,8 +514,8 @@ int damn_autotune(damn_mat A, int32_t nrhs, const void* X, void* Y, int32_t reps
 
 typedef struct damn_mlp_s* damn_mlp;
 
-/* Network 16 -> 64 -> 64 -> 49 (ReLU), float32 on the device.  params
- * (host, DAMN_MLP_NPARAMS floats: W1[64][16], b1, W2[64][64], b2, W3[49][64],
+/* Network 16 -> 64 -> 64 -> 70 (ReLU), float32 on the device.  params
+ * (host, DAMN_MLP_NPARAMS floats: W1[64][16], b1, W2[64][64], b2, W3[70][64],
  * b3, then the feature standardisation mu[16], sigma[16]) or NULL for a
  * seeded He-uniform initialisation. */
 int damn_mlp_create(damn_mlp* out, const float* params, uint64_t seed);
@@ -509,13 +523,13 @@ int damn_mlp_get_params(damn_mlp M, float* params);
 int damn_mlp_destroy(damn_mlp M);
 
 /* Loss and parameter gradients on one minibatch (for checking the backward
- * kernels): feats[B][16], targets[B][49] (a distribution over the classes
+ * kernels): feats[B][16], targets[B][70] (a distribution over the classes
  * that apply; feats[b][9] = nrhs decides which apply), host arrays; the
  * gradients of mu and sigma are returned as 0. */
 int damn_mlp_grad(damn_mlp M, int32_t B, const float* feats, const float* targets, float* loss,
                   float* grads, void* stream);
 
-/* Train on N samples: feats[N][16] and autotuner times[N][49] (+inf where a
+/* Train on N samples: feats[N][16] and autotuner times[N][70] (+inf where a
  * class does not apply), host arrays.  Sets mu/sigma from the features, then
  * runs `epochs` passes of Adam over shuffled minibatches of `batch` samples
  * with soft targets q_c ~ exp(-(t_c/t_min - 1)/tau).  epoch_loss[epochs]

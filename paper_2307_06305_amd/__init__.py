@@ -379,6 +379,13 @@ class Matrix:
     def is_da(self):
         return FORMATS[self.format][1]
 
+    @property
+    def takes_paired(self):
+        """Whether the stream variant's paired gathers apply (unroll 2):
+        DA16 and CSR32 handles with float64 or float32 values."""
+        return (self.format in (FORMAT_DA16, FORMAT_CSR32) and self.dtype in (F64, F32)
+                and self.block == 1)
+
     def apply(self, x, y, alpha=1.0, beta=0.0, stream=None):
         """spmv or csr_spmv, whichever matches the handle's format."""
         f = self.spmv if self.is_da else self.csr_spmv
@@ -500,7 +507,8 @@ class Batch:
             pass
 
 
-NFEAT, NCLASS, MLP_NPARAMS = 16, 49, 8465
+NFEAT, NCLASS, MLP_NPARAMS = 16, 70, 9830
+CLASS_SPMM = 63  # first SpMM class; 0..62 are single-vector products
 
 
 def features(nrows, ncols, rowptr, colids, nrhs):
@@ -564,7 +572,7 @@ class Mlp:
         Q = np.ascontiguousarray(targets, dtype=np.float32)
         B = F.shape[0]
         if F.shape != (B, NFEAT) or Q.shape != (B, NCLASS):
-            raise ValueError("feats (B, 16) and targets (B, 49)")
+            raise ValueError(f"feats (B, 16) and targets (B, {NCLASS})")
         loss = C.c_float()
         g = np.empty(MLP_NPARAMS, dtype=np.float32)
         _check(lib.damn_mlp_grad(self._h, B, F.ctypes.data_as(C.c_void_p),
@@ -578,7 +586,7 @@ class Mlp:
         T = np.ascontiguousarray(times, dtype=np.float32)
         N = F.shape[0]
         if F.shape != (N, NFEAT) or T.shape != (N, NCLASS):
-            raise ValueError("feats (N, 16) and times (N, 49)")
+            raise ValueError(f"feats (N, 16) and times (N, {NCLASS})")
         losses = np.empty(epochs, dtype=np.float32)
         _check(lib.damn_mlp_train(self._h, N, F.ctypes.data_as(C.c_void_p),
                                   T.ctypes.data_as(C.c_void_p), int(epochs), int(batch),

@@ -292,6 +292,7 @@ int run_spmv(damn_mat A, const void* x, void* y, double alpha, double beta, void
     a.cap = A->tiles_cap;
     a.tile_rows = A->tiles_rows;
     a.cache = A->cfg.cache;
+    a.gather = gather_of(A->cfg);
   }
   const hipError_t e = launch_spmv(a, A->cfg.variant, A->cfg.lanes, A->cfg.unroll);
   return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
@@ -580,11 +581,13 @@ int damn_set_config(damn_mat A, const damn_config* cfg) {
   } else {
     if (c.tile < 256 || c.tile > 4096 || (c.tile % 8) != 0) return DAMN_ERR_UNSUPPORTED;
     if (c.cache != DAMN_CACHE_NT && c.cache != DAMN_CACHE_PLAIN) return DAMN_ERR_INVALID_ARG;
-    if (c.cache == DAMN_CACHE_PLAIN &&
-        (A->block > 1 || (A->format != DAMN_FORMAT_DA16 && A->format != DAMN_FORMAT_CSR32) ||
-         (A->dtype != DAMN_F64 && A->dtype != DAMN_F32)))
-      return DAMN_ERR_UNSUPPORTED;
+    const bool plain_cell = A->block == 1 &&
+                            (A->format == DAMN_FORMAT_DA16 || A->format == DAMN_FORMAT_CSR32) &&
+                            (A->dtype == DAMN_F64 || A->dtype == DAMN_F32);
+    if (c.cache == DAMN_CACHE_PLAIN && !plain_cell) return DAMN_ERR_UNSUPPORTED;
     if (c.unroll == 0) c.unroll = 1;
+    if (c.unroll != 1 && c.unroll != 2) return DAMN_ERR_INVALID_ARG;
+    if (c.unroll == 2 && !plain_cell) return DAMN_ERR_UNSUPPORTED;
     const int st = build_tiles(A, tile_cap(A, c.tile), nullptr);
     if (st != DAMN_OK) return st;
   }

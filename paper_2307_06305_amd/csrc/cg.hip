@@ -394,6 +394,7 @@ SpmvArgs stream_args(damn_mat A, const void* x, void* y, double alpha, double be
   a.ntiles = A->ntiles;
   a.cap = A->tiles_cap;
   a.tile_rows = A->tiles_rows;
+  a.gather = gather_of(A->cfg);
   a.stream = s;
   return a;
 }

@@ -59,6 +59,7 @@ struct SpmvArgs {
   int64_t nchunks = 0;
   // stream variant
   int32_t cache = DAMN_CACHE_NT;  // cache policy of the matrix stream (damn_cache)
+  int32_t gather = 1;             // x values per gather load: 1 interleaved, 2 paired
   const TileStart* tile_row = nullptr;
   int64_t ntiles = 0;
   int32_t cap = 0;

@@ -35,6 +35,11 @@ struct damn_mat_s {
 };
 
 namespace damn {
+// x values per gather load of a stream configuration: its `unroll` (1
+// interleaved, 2 paired); 1 for the vector variant.
+inline int32_t gather_of(const damn_config& c) {
+  return c.variant == DAMN_VAR_STREAM && c.unroll == 2 ? 2 : 1;
+}
 // Build (or reuse) the stream tiles of A for entry cap `cap`; synchronises.
 int build_tiles(damn_mat A, int32_t cap, hipStream_t s);
 // Free the conjugate-gradient workspace of A, if any.

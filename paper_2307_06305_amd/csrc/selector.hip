@@ -1,13 +1,15 @@
 // Launch-configuration selection: the exhaustive autotuner and a small
 // multilayer perceptron that predicts its choice from sparsity features.
 //
-// Classes (DAMN_NCLASS = 49):
+// Classes (DAMN_NCLASS = 70):
 //   0..20   vector variant, lanes {1,2,4,...,64} x unroll {1,2,4}  (nrhs = 1)
-//   21..41  stream variant, lanes {1,...,64} x tile {1024,2048,4096} (nrhs = 1)
-//   42..48  SpMM (stream, 2048-entry tiles), lanes {1,...,64}        (nrhs > 1)
+//   21..41  stream variant, interleaved gathers, lanes {1,...,64} x tile
+//           {1024,2048,4096}                                        (nrhs = 1)
+//   42..62  stream variant, paired gathers, the same lanes x tiles  (nrhs = 1)
+//   63..69  SpMM (stream, 2048-entry tiles), lanes {1,...,64}        (nrhs > 1)
 //
 // Network: x = (f - mu) / sigma (16 features), h1 = relu(W1 x + b1) (64),
-// h2 = relu(W2 h1 + b2) (64), z = W3 h2 + b3 (49); classes that do not apply
+// h2 = relu(W2 h1 + b2) (64), z = W3 h2 + b3 (70); classes that do not apply
 // to the sample's nrhs are masked out of the softmax.  Training minimises the
 // cross entropy against soft targets q_c ~ exp(-(t_c / t_min - 1) / tau)
 // built from autotuner times, with Adam.  All network arithmetic runs in
@@ -34,22 +36,24 @@ namespace sel {
 
 constexpr int F = DAMN_NFEAT;    // 16
 constexpr int H = 64;            // hidden width
-constexpr int K = DAMN_NCLASS;   // 49
+constexpr int K = DAMN_NCLASS;   // 70
+constexpr int kSpmm0 = DAMN_CLASS_SPMM;  // first SpMM class
 constexpr int kW1 = 0, kB1 = kW1 + H * F, kW2 = kB1 + H, kB2 = kW2 + H * H, kW3 = kB2 + H,
               kB3 = kW3 + K * H, kMu = kB3 + K, kSigma = kMu + F, kTotal = kSigma + F;
 constexpr int kTrained = kMu;    // parameters before mu/sigma are trained
 static_assert(kTotal == DAMN_MLP_NPARAMS, "parameter layout");
+static_assert(K <= 2 * H, "a workgroup of H threads handles at most two classes per thread");
 
 constexpr int kLanes[7] = {1, 2, 4, 8, 16, 32, 64};
 constexpr int kUnrolls[3] = {1, 2, 4};
 constexpr int kTiles[3] = {1024, 2048, 4096};
 
 __device__ __forceinline__ bool class_valid(int k, float nrhs) {
-  return nrhs > 1.5f ? k >= 42 : k < 42;
+  return nrhs > 1.5f ? k >= kSpmm0 : k < kSpmm0;
 }
 
-// Forward pass of one sample (64 threads); leaves x, h1, h2, z in LDS and,
-// if `save` is set, in the activation arrays at row `row`.
+// Forward pass of one sample (H = 64 threads; thread t computes the logits
+// of classes t and t + H); leaves x, h1, h2, z in LDS.
 __device__ void forward_one(const float* __restrict__ P, const float* __restrict__ f,
                             float* xs, float* h1, float* h2, float* z) {
   const int t = threadIdx.x;
@@ -63,10 +67,10 @@ __device__ void forward_one(const float* __restrict__ P, const float* __restrict
   for (int i = 0; i < H; ++i) a += P[kW2 + t * H + i] * h1[i];
   h2[t] = a > 0.f ? a : 0.f;
   __syncthreads();
-  if (t < K) {
-    a = P[kB3 + t];
-    for (int i = 0; i < H; ++i) a += P[kW3 + t * H + i] * h2[i];
-    z[t] = a;
+  for (int k = t; k < K; k += H) {
+    a = P[kB3 + k];
+    for (int i = 0; i < H; ++i) a += P[kW3 + k * H + i] * h2[i];
+    z[k] = a;
   }
   __syncthreads();
 }
@@ -82,14 +86,13 @@ __global__ __launch_bounds__(64) void fwd_bwd(const float* __restrict__ P,
                                               float* __restrict__ A2, float* __restrict__ dZ,
                                               float* __restrict__ dH2, float* __restrict__ dH1,
                                               float* __restrict__ loss) {
-  __shared__ float xs[F], h1[H], h2[H], z[H], dz[H], dh2[H];
+  __shared__ float xs[F], h1[H], h2[H], z[K], dz[K], dh2[H], terms[K];
   __shared__ float red[2];
   const int b = blockIdx.x, t = threadIdx.x;
   const int s = idx[b];
   const float* f = feats + int64_t(s) * F;
   forward_one(P, f, xs, h1, h2, z);
   const float nrhs = f[9];
-  const bool valid = t < K && class_valid(t, nrhs);
   // masked softmax (lane 0 does the small reductions in a fixed order)
   if (t == 0) {
     float m = -INFINITY;
@@ -102,17 +105,19 @@ __global__ __launch_bounds__(64) void fwd_bwd(const float* __restrict__ P,
     red[1] = sum;
   }
   __syncthreads();
-  const float q = t < K ? targets[int64_t(s) * K + t] : 0.f;
-  float p = 0.f;
-  if (valid) p = expf(z[t] - red[0]) / red[1];
-  dz[t] = valid ? (p - q) / float(B) : 0.f;
-  // loss term -q log p, log p = z - m - log(sum)
-  const float lterm = (valid && q > 0.f) ? -q * (z[t] - red[0] - logf(red[1])) : 0.f;
+  for (int k = t; k < K; k += H) {
+    const bool valid = class_valid(k, nrhs);
+    const float q = targets[int64_t(s) * K + k];
+    const float p = valid ? expf(z[k] - red[0]) / red[1] : 0.f;
+    dz[k] = valid ? (p - q) / float(B) : 0.f;
+    // loss term -q log p, log p = z - m - log(sum)
+    terms[k] = (valid && q > 0.f) ? -q * (z[k] - red[0] - logf(red[1])) : 0.f;
+  }
   __syncthreads();
   if (t < F) X[b * F + t] = xs[t];
   A1[b * H + t] = h1[t];
   A2[b * H + t] = h2[t];
-  if (t < K) dZ[b * K + t] = dz[t];
+  for (int k = t; k < K; k += H) dZ[b * K + k] = dz[k];
   // dH2 = W3^T dZ masked by relu; dH1 = W2^T dH2 masked by relu
   float g = 0.f;
   for (int k = 0; k < K; ++k) g += P[kW3 + k * H + t] * dz[k];
@@ -123,10 +128,7 @@ __global__ __launch_bounds__(64) void fwd_bwd(const float* __restrict__ P,
   g = 0.f;
   for (int j = 0; j < H; ++j) g += P[kW2 + j * H + t] * dh2[j];
   dH1[b * H + t] = h1[t] > 0.f ? g : 0.f;
-  // per-sample loss: sum of the lane terms in lane order
-  __shared__ float terms[H];
-  terms[t] = lterm;
-  __syncthreads();
+  // per-sample loss: sum of the class terms in class order
   if (t == 0) {
     float l = 0.f;
     for (int k = 0; k < K; ++k) l += terms[k];
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(64) void select_cls(const float* __restrict__ P,
                                                  const float* __restrict__ feats,
                                                  int32_t* __restrict__ out,
                                                  float* __restrict__ prob) {
-  __shared__ float xs[F], h1[H], h2[H], z[H];
+  __shared__ float xs[F], h1[H], h2[H], z[K];
   const int s = blockIdx.x;
   const float* f = feats + int64_t(s) * F;
   forward_one(P, f, xs, h1, h2, z);
@@ -355,14 +357,15 @@ int damn_class_config(int32_t cls, damn_config* cfg, int32_t* spmm) {
     c.lanes = sel::kLanes[cls / 3];
     c.unroll = sel::kUnrolls[cls % 3];
     c.tile = 2048;
-  } else if (cls < 42) {
+  } else if (cls < sel::kSpmm0) {
+    const int32_t j = (cls - 21) % 21;
     c.variant = DAMN_VAR_STREAM;
-    c.lanes = sel::kLanes[(cls - 21) / 3];
-    c.unroll = 1;
-    c.tile = sel::kTiles[(cls - 21) % 3];
+    c.lanes = sel::kLanes[j / 3];
+    c.unroll = cls < 42 ? 1 : 2;  // interleaved or paired gathers
+    c.tile = sel::kTiles[j % 3];
   } else {
     c.variant = DAMN_VAR_STREAM;  // the stream SpMM, 2048-entry tiles
-    c.lanes = sel::kLanes[cls - 42];
+    c.lanes = sel::kLanes[cls - sel::kSpmm0];
     c.unroll = 1;
     c.tile = 2048;
     mm = 1;
@@ -393,6 +396,10 @@ int damn_autotune(damn_mat A, int32_t nrhs, const void* X, void* Y, int32_t reps
     damn_class_config(k, &c, &mm);
     if ((nrhs > 1) != (mm != 0)) continue;
     st = damn_set_config(A, &c);
+    if (st == DAMN_ERR_UNSUPPORTED && c.unroll == 2 && c.variant == DAMN_VAR_STREAM) {
+      st = DAMN_OK;  // paired gathers do not apply to this handle's cell
+      continue;
+    }
     if (st != DAMN_OK) break;
     auto once = [&]() {
       if (nrhs > 1) return damn_spmm(A, X, Y, nrhs, 1.0, 0.0, stream);

@@ -83,7 +83,8 @@ __global__ __launch_bounds__(256) void spmv_vector(
 //      is aligned.  The entry loads carry the non-temporal hint: the matrix is
 //      read once, and keeping it from displacing x in L2 means each x line is
 //      fetched from HBM once;
-//   2. reduces each row from LDS with G lanes per row, gathering x.
+//   2. reduces each row from LDS with G lanes per row, gathering x one value
+//      per load (interleaved) or two neighbouring values per load (paired).
 // Step 1 streams at full load width whatever the row lengths; step 2 puts
 // neighbouring rows on neighbouring lanes, so for banded matrices the x
 // gathers of one instruction hit few cache lines.
@@ -111,18 +112,95 @@ struct TileLds {
   }
 };
 
+// Phase 2 of the stream kernel for one row whose entries sit at LDS
+// positions [s, e): the share of lane `part` (0 <= part < G) of the row's sum.
+//
+// Interleaved gathers (one x value per load): the lane takes entries
+// s + part, s + part + G, ... with four independent partial sums.
+template <int G, typename I, typename V, typename S>
+__device__ __forceinline__ V row_interleaved(const S* __restrict__ val_s,
+                                             const I* __restrict__ idx_s, int32_t s, int32_t e,
+                                             int part, const V* __restrict__ xs) {
+  V acc[4] = {V(0), V(0), V(0), V(0)};
+  int32_t k = s + part;
+  for (; k + 3 * G < e; k += 4 * G) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] += V(val_s[k + u * G]) * xs[idx_s[k + u * G]];
+  }
+#pragma unroll
+  for (int u = 0; u < 3; ++u)
+    if (k + u * G < e) acc[u] += V(val_s[k + u * G]) * xs[idx_s[k + u * G]];
+  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+// Paired gathers (two x values per load): the lane takes the contiguous
+// chunk of h = ceil((e - s) / G) entries starting at s + part * h and walks
+// it greedily.  Each step loads x[c] and x[c + 1] with one load and also
+// uses the second value when the next entry's column is c + 1, so a run of
+// neighbouring columns (three per stencil line) costs one load per two
+// entries.  cb is the column base (the row for DA offsets, 0 for CSR
+// columns); the load address is clamped to `last` = ncols - 2 (ncols >= 2),
+// so no load reads past x.  Up to four steps are in flight per lane.  The
+// positions read past the chunk (at most e + 1) lie inside the tile's LDS
+// slots, and what they hold is never used.
+template <int G, typename I, typename V, typename S>
+__device__ __forceinline__ V row_paired(const S* __restrict__ val_s, const I* __restrict__ idx_s,
+                                        int32_t s, int32_t e, int part,
+                                        const V* __restrict__ x, int32_t cb, int32_t last) {
+  typedef V V2 __attribute__((ext_vector_type(2), aligned(sizeof(V))));
+  constexpr int U = 4;
+  const int32_t h = (e - s + G - 1) / G;
+  int32_t k = s + part * h;
+  const int32_t kend = min(e, k + h);
+  V acc0 = V(0), acc1 = V(0);
+  while (k < kend) {
+    int32_t kk[U], la[U];
+    bool in[U], pr[U], hi[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t o0 = int32_t(idx_s[k]), o1 = int32_t(idx_s[k + 1]);
+      in[u] = k < kend;
+      pr[u] = in[u] && k + 1 < kend && o1 == o0 + 1;
+      const int32_t c = cb + o0;
+      la[u] = min(c, last);
+      hi[u] = c != la[u];  // only the last column: its value is the pair's second
+      kk[u] = k;
+      k += in[u] ? (pr[u] ? 2 : 1) : 0;
+    }
+    V2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (in[u])
+        __builtin_memcpy(&v[u], x + la[u], sizeof(V2));
+      else
+        v[u] = V2{V(0), V(0)};
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      // selects, not multiplications by zero: an unused value may be inf
+      const V f0 = acc0 + V(val_s[kk[u]]) * (hi[u] ? v[u].y : v[u].x);
+      const V f1 = acc1 + V(val_s[kk[u] + 1]) * v[u].y;
+      acc0 = in[u] ? f0 : acc0;
+      acc1 = pr[u] ? f1 : acc1;
+    }
+  }
+  return acc0 + acc1;
+}
+
 // Optional epilogue for conjugate gradients (DOT): each workgroup also writes
 // partial[t] = sum over its rows of y_r * w_r in float64 (w = nullptr means
 // w = y), and every workgroup returns at once when *done is nonzero.
 // AUX is the cache policy of the entry arrays' copies: non-temporal by
 // default, plain (AUX = 0) for products whose whole working set fits the
 // MALL, where caching the matrix lets repeated products read it from there.
+// X is the number of x values per gather load: 1 for interleaved gathers,
+// 2 for paired ones (then `last` = ncols - 2 >= 0).
 template <typename I, typename V, bool DA, int G, bool DOT = false, typename S = V,
-          int AUX = kNonTemporal>
+          int AUX = kNonTemporal, int X = 1>
 __global__ __launch_bounds__(256) void spmv_stream(
     const TileStart* __restrict__ tile_row, const int32_t* __restrict__ rowptr,
     const I* __restrict__ idx, const S* __restrict__ val, const V* __restrict__ x,
-    V* __restrict__ y, V alpha, V beta, int32_t read_y, int32_t cap,
+    V* __restrict__ y, V alpha, V beta, int32_t read_y, int32_t cap, int32_t last,
     const V* __restrict__ w = nullptr, double* __restrict__ partial = nullptr,
     const int32_t* __restrict__ done = nullptr) {
   using L = TileLds<I, S>;
@@ -175,8 +253,8 @@ __global__ __launch_bounds__(256) void spmv_stream(
   __syncthreads();
 
   // 2. G lanes per row.  Within a wave, lane l takes row l mod (64/G) of the
-  //    wave's rows and part l / (64/G) of that row, so four neighbouring
-  //    lanes hold four neighbouring rows at the same entry position: for a
+  //    wave's rows and part l / (64/G) of that row, so neighbouring lanes
+  //    hold neighbouring rows at the same position of their parts: for a
   //    banded matrix their x gathers are adjacent words, which the vector
   //    cache serves as one access.
   constexpr int RPW = 64 / G;  // rows per wave and pass
@@ -185,20 +263,14 @@ __global__ __launch_bounds__(256) void spmv_stream(
   double dot = 0.0;
   for (int32_t r = r0 + int32_t(threadIdx.x >> 6) * RPW + (wl % RPW); r < r1; r += 256 / G) {
     const int32_t s = rp_s[r - ar] - a0, e = rp_s[r + 1 - ar] - a0;
-    const V* xs = DA ? x + r : x;
     // the dot epilogue's w_r, loaded with the row's gathers rather than
     // after its sum
     const V wr = (DOT && w && lane == 0) ? w[r] : V(0);
-    V acc[4] = {V(0), V(0), V(0), V(0)};
-    int32_t k = s + lane;
-    for (; k + 3 * G < e; k += 4 * G) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] += V(val_s[k + u * G]) * xs[idx_s[k + u * G]];
-    }
-#pragma unroll
-    for (int u = 0; u < 3; ++u)
-      if (k + u * G < e) acc[u] += V(val_s[k + u * G]) * xs[idx_s[k + u * G]];
-    V sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    V sum;
+    if constexpr (X == 2)
+      sum = row_paired<G>(val_s, idx_s, s, e, lane, x, DA ? r : 0, last);
+    else
+      sum = row_interleaved<G>(val_s, idx_s, s, e, lane, DA ? x + r : x);
     if (G > 1) sum = strided_group_sum<G>(sum);
     if (lane == 0) {
       const V yr = finish(sum, alpha, beta, read_y != 0, y + r);
@@ -281,25 +353,45 @@ template <typename I, typename S, bool DA>
 constexpr bool kHasPlainStream =
     (DA ? sizeof(I) == 2 : sizeof(I) == 4) && (sizeof(S) == 8 || sizeof(S) == 4);
 
+// Paired gathers run where the cell has the plain-stream kernels and the
+// matrix has at least two columns (the host rejects paired configurations
+// of other cells; a one-column matrix takes the interleaved kernel).
+template <typename I, typename S, bool DA>
+bool use_paired(const SpmvArgs& a) {
+  return kHasPlainStream<I, S, DA> && a.gather == 2 && a.ncols >= 2;
+}
+
 template <typename I, typename S, typename V, bool DA, int G>
 hipError_t stream_g(const SpmvArgs& a) {
   if (a.ntiles == 0) return hipSuccess;
+  const dim3 grid(uint32_t(a.ntiles)), block(256);
+  const size_t lds = kern::TileLds<I, S>::bytes(a.cap, a.tile_rows);
+  const I* idx = static_cast<const I*>(a.idx);
+  const S* val = static_cast<const S*>(a.val);
+  const V* x = static_cast<const V*>(a.x);
+  V* y = static_cast<V*>(a.y);
   if constexpr (kHasPlainStream<I, S, DA>) {
     if (a.cache == DAMN_CACHE_PLAIN) {
-      hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, false, S, 0>), dim3(uint32_t(a.ntiles)),
-                         dim3(256), (kern::TileLds<I, S>::bytes(a.cap, a.tile_rows)), a.stream,
-                         a.tile_row, a.rowptr, static_cast<const I*>(a.idx),
-                         static_cast<const S*>(a.val), static_cast<const V*>(a.x),
-                         static_cast<V*>(a.y), V(a.alpha), V(a.beta), a.read_y, a.cap, nullptr,
-                         nullptr, nullptr);
+      if (use_paired<I, S, DA>(a))
+        hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, false, S, 0, 2>), grid, block, lds,
+                           a.stream, a.tile_row, a.rowptr, idx, val, x, y, V(a.alpha),
+                           V(a.beta), a.read_y, a.cap, a.ncols - 2, nullptr, nullptr, nullptr);
+      else
+        hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, false, S, 0>), grid, block, lds,
+                           a.stream, a.tile_row, a.rowptr, idx, val, x, y, V(a.alpha),
+                           V(a.beta), a.read_y, a.cap, 0, nullptr, nullptr, nullptr);
+      return hipGetLastError();
+    }
+    if (use_paired<I, S, DA>(a)) {
+      hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, false, S, kern::kNonTemporal, 2>), grid,
+                         block, lds, a.stream, a.tile_row, a.rowptr, idx, val, x, y, V(a.alpha),
+                         V(a.beta), a.read_y, a.cap, a.ncols - 2, nullptr, nullptr, nullptr);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, false, S>), dim3(uint32_t(a.ntiles)),
-                     dim3(256), (kern::TileLds<I, S>::bytes(a.cap, a.tile_rows)), a.stream, a.tile_row,
-                     a.rowptr, static_cast<const I*>(a.idx), static_cast<const S*>(a.val),
-                     static_cast<const V*>(a.x), static_cast<V*>(a.y), V(a.alpha), V(a.beta),
-                     a.read_y, a.cap, nullptr, nullptr, nullptr);
+  hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, false, S>), grid, block, lds, a.stream,
+                     a.tile_row, a.rowptr, idx, val, x, y, V(a.alpha), V(a.beta), a.read_y, a.cap,
+                     0, nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -319,11 +411,22 @@ hipError_t stream(const SpmvArgs& a, int lanes) {
 template <typename I, typename V, bool DA, int G>
 hipError_t stream_dot_g(const SpmvArgs& a, const void* w, double* partial, const int32_t* done) {
   if (a.ntiles == 0) return hipSuccess;
-  hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, true, V>), dim3(uint32_t(a.ntiles)),
-                     dim3(256), (kern::TileLds<I, V>::bytes(a.cap, a.tile_rows)), a.stream, a.tile_row,
-                     a.rowptr, static_cast<const I*>(a.idx), static_cast<const V*>(a.val),
-                     static_cast<const V*>(a.x), static_cast<V*>(a.y), V(a.alpha), V(a.beta),
-                     a.read_y, a.cap, static_cast<const V*>(w), partial, done);
+  const dim3 grid(uint32_t(a.ntiles)), block(256);
+  const size_t lds = kern::TileLds<I, V>::bytes(a.cap, a.tile_rows);
+  const I* idx = static_cast<const I*>(a.idx);
+  const V* val = static_cast<const V*>(a.val);
+  const V* x = static_cast<const V*>(a.x);
+  V* y = static_cast<V*>(a.y);
+  if (use_paired<I, V, DA>(a)) {
+    hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, true, V, kern::kNonTemporal, 2>), grid,
+                       block, lds, a.stream, a.tile_row, a.rowptr, idx, val, x, y, V(a.alpha),
+                       V(a.beta), a.read_y, a.cap, a.ncols - 2, static_cast<const V*>(w), partial,
+                       done);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, true, V>), grid, block, lds, a.stream,
+                     a.tile_row, a.rowptr, idx, val, x, y, V(a.alpha), V(a.beta), a.read_y, a.cap,
+                     0, static_cast<const V*>(w), partial, done);
   return hipGetLastError();
 }
 

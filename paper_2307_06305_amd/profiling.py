@@ -35,19 +35,21 @@ CSR_LAUNCH = "stream_g2_t2048"
 
 
 def stream_launch(name):
-    """(lanes, tile) of a stream launch name such as stream_g2_t4096."""
-    m = re.fullmatch(r"stream_g(\d+)_t(\d+)", name)
+    """(lanes, tile, gather) of a stream launch name: stream_gG_tT for
+    interleaved gathers (gather 1), paired_gG_tT for paired ones (2)."""
+    m = re.fullmatch(r"(stream|paired)_g(\d+)_t(\d+)", name)
     if not m:
         raise ValueError(f"not a stream launch name: {name!r}")
-    return int(m.group(1)), int(m.group(2))
+    return int(m.group(2)), int(m.group(3)), 2 if m.group(1) == "paired" else 1
 
 
 def kernel_name(label, launch):
-    g, _ = stream_launch(launch)
+    g, _, x = stream_launch(launch)
     index = "short" if label == "da" else "int"
-    # the last template argument is the matrix stream's cache policy (2: non-temporal)
+    # the last two template arguments are the matrix stream's cache policy
+    # (2: non-temporal) and the x values per gather load
     return (f"spmv_stream<{index}, double, {'true' if label == 'da' else 'false'}, {g}, false, "
-            f"double, 2>")
+            f"double, 2, {x}>")
 COPY_KERNEL = "stream_copy"
 
 

@@ -6,7 +6,7 @@ the GPU, evaluate it, load the shipped weights.
     python -m paper_2307_06305_amd.selector evaluate --data times.npz --weights weights.npy
 
 Each generated matrix gives two samples: its SpMV timings (nrhs = 1,
-classes 0..41) and its SpMM timings for its own nrhs (2..8, classes 42..48).
+classes 0..62) and its SpMM timings for its own nrhs (2..8, classes 63..69).
 All timing is done by the library's autotuner, all network arithmetic by the
 library's kernels.
 """
@@ -21,8 +21,8 @@ import time
 
 import numpy as np
 
-from . import (F64, MLP_NPARAMS, NCLASS, NFEAT, VAR_STREAM, Matrix, Mlp, autotune, encode,
-               features)
+from . import (CLASS_SPMM, F64, MLP_NPARAMS, NCLASS, NFEAT, VAR_STREAM, Matrix, Mlp, autotune,
+               encode, features)
 
 DATA_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
 WEIGHTS = os.path.join(DATA_DIR, "selector_weights.npy")
@@ -36,9 +36,10 @@ def config_class(cfg, nrhs):
     """Class index of a handle configuration (as get_config returns it)."""
     li = LANES.index(cfg["lanes"])
     if nrhs > 1:
-        return 42 + li
+        return CLASS_SPMM + li
     if cfg["variant"] == VAR_STREAM:
-        return 21 + 3 * li + TILES.index(cfg["tile"])
+        paired = 21 if cfg["unroll"] == 2 else 0
+        return 21 + paired + 3 * li + TILES.index(cfg["tile"])
     return 3 * li + (1, 2, 4).index(cfg["unroll"])
 
 

@@ -10,7 +10,7 @@ import paper_2307_06305_amd as D
 from gpu_util import U32, U64, assert_within, dev, error_bound, host, torch_or_skip
 from oracle import blocks as OB
 from oracle import storage as OST
-from paper_2307_06305_amd.tuning import candidates, config_name
+from paper_2307_06305_amd.tuning import candidates_for, config_name
 from workloads import laplace_2d_5pt, random_csr, uniform_vector
 from workloads.matrices import CSR, block_stencil_27pt
 
@@ -85,7 +85,7 @@ def test_bsr_all_configs_match_oracle(b, A, fmt, store):
     for alpha, beta in ((1.0, 0.0), (-1.5, 0.25)):
         ref = OB.spmv_bsr(nbr, nbc, b, brp, bcols, bv, x, alpha, beta, y0, da=False)
         bnd = error_bound(A.nrows, srp, scols, svals, x, alpha, beta, y0, U64 if f64 else U32)
-        for cfg in candidates():
+        for cfg in candidates_for(M):
             yd = dev(y0, tdt)
             M.set_config(*cfg)
             M.apply(xd, yd, alpha, beta)
@@ -112,7 +112,7 @@ def test_bsr_kronecker_laplacian_closed_form(b):
     for store, tdt in ((D.F64, torch.float64), (D.F32, torch.float32)):
         M = D.Matrix.bsr_create(D.FORMAT_DABSR16, nbr, nbr, b, A.rowptr, off, bvals, store=store)
         xd = dev(x, tdt)
-        for cfg in candidates():
+        for cfg in candidates_for(M):
             yd = torch.full((nbr * b,), np.nan, dtype=tdt, device="cuda")
             M.set_config(*cfg)
             M.apply(xd, yd)
@@ -164,7 +164,7 @@ def test_bsr_full_size_every_row(fmt):
     bnd = error_bound(A.nrows, A.rowptr, A.colids, A.vals, x, 1.0, 0.0, None, U64)
     xd = dev(x)
     yd = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
-    for cfg in candidates():
+    for cfg in candidates_for(M):
         print(f"case block3 {fmt} {config_name(cfg)}", flush=True)
         yd.fill_(float("nan"))
         M.set_config(*cfg)

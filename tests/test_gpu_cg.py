@@ -119,18 +119,21 @@ def _split_diagonal(A):
 @pytest.mark.parametrize("fmt", ["da", "csr"])
 @pytest.mark.parametrize("lanes", [1, 2, 4, 16])
 @pytest.mark.parametrize("split", [False, True])
-def test_cg_dot_epilogue_lanes_and_split_diagonal(fmt, lanes, split):
+@pytest.mark.parametrize("gather", [1, 2])
+def test_cg_dot_epilogue_lanes_and_split_diagonal(fmt, lanes, split, gather):
     """The SpMV with the p.Ap epilogue at every lane count of the stream
-    kernel (lanes of a row spread over the wave), on the 2D Laplacian and on
-    the same operator with some diagonals stored as two entries: the solve
-    matches the oracle's CG on the same matrix."""
+    kernel (lanes of a row spread over the wave), with interleaved and paired
+    gathers, on the 2D Laplacian and on the same operator with some
+    diagonals stored as two entries: the solve matches the oracle's CG on
+    the same matrix, and the mixed solve reaches the float64 residual."""
     torch_or_skip()
     A = laplace_2d_5pt(40)
     if split:
         A = _split_diagonal(A)
     b = uniform_vector(A.nrows, 33)
     A64, A32 = _handles(A, fmt)
-    A64.set_config(D.VAR_STREAM, lanes, 1, 1024)
+    A64.set_config(D.VAR_STREAM, lanes, gather, 1024)
+    A32.set_config(D.VAR_STREAM, lanes, gather, 1024)
     xd = dev(np.zeros(A.nrows))
     info = D.cg(A64, dev(b), xd, tol=1e-10, check_every=7)
     ref = OC.cg_fp64(lambda v: OS.spmv_csr(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, v), b)
@@ -139,6 +142,9 @@ def test_cg_dot_epilogue_lanes_and_split_diagonal(fmt, lanes, split):
     assert rr <= 1.05e-10
     assert abs(info["rel_res"] - rr) <= 1e-12
     assert abs(info["iters"] - ref["iters"]) <= 2
+    xm = dev(np.zeros(A.nrows))
+    info = D.cg(A64, dev(b), xm, A32=A32, tol=1e-10, inner_tol=1e-5, check_every=5)
+    assert info["converged"] and _true_rel_res(A, host(xm), b) <= 1e-10
     A64.destroy()
     A32.destroy()
 

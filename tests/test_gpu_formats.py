@@ -10,7 +10,7 @@ import paper_2307_06305_amd as D
 from gpu_util import U32, U64, assert_within, dev, error_bound, host, torch_or_skip
 from oracle import spmv as OS
 from oracle import storage as OST
-from paper_2307_06305_amd.tuning import candidates, config_name
+from paper_2307_06305_amd.tuning import candidates_for, config_name
 from workloads import laplace_2d_5pt, random_banded, random_csr, stencil_3d_27pt, uniform_vector
 from workloads.matrices import CSR, stencil_3d_27pt_box
 
@@ -92,7 +92,7 @@ def test_grid_all_configs_match_oracle(A, fmt, vt):
     for alpha, beta in ((1.0, 0.0), (0.5, -2.0)):
         ref = _oracle(fmt, A, idx, vals, x, alpha, beta, y0)
         bnd = error_bound(A.nrows, A.rowptr, cols, vals, x, alpha, beta, y0, u)
-        for cfg in candidates():
+        for cfg in candidates_for(M):
             yd = dev(y0, tdt)
             M.set_config(*cfg)
             M.apply(xd, yd, alpha, beta)
@@ -118,7 +118,7 @@ def test_grid_laplacian_closed_form_bit_exact(fmt, vt):
     tdt = torch.float64 if vt == "f64" else torch.float32
     M = _upload(fmt, vt, A)
     xd = dev(x, tdt)
-    for cfg in candidates():
+    for cfg in candidates_for(M):
         yd = torch.full((A.nrows,), np.nan, dtype=tdt, device="cuda")
         M.set_config(*cfg)
         M.apply(xd, yd)  # beta = 0: the NaNs in y are not read
@@ -205,7 +205,7 @@ def test_grid_full_size_box_every_row(fmt, vt):
     tdt = torch.float64 if f64 else torch.float32
     xd = dev(x, tdt)
     yd = torch.empty(A.nrows, dtype=tdt, device="cuda")
-    for cfg in candidates():
+    for cfg in candidates_for(M):
         print(f"case box {fmt} {vt} {config_name(cfg)}", flush=True)
         yd.fill_(float("nan"))
         M.set_config(*cfg)

@@ -18,7 +18,7 @@ import pytest
 import paper_2307_06305_amd as D
 from gpu_util import U64, assert_within, dev, error_bound, host, torch_or_skip
 from oracle import spmv as OS
-from paper_2307_06305_amd.tuning import candidates, config_name
+from paper_2307_06305_amd.tuning import candidates_for, config_name
 from workloads import config_matrix, config_vector
 from workloads.matrices import batch_matrix, batch_member
 
@@ -39,7 +39,7 @@ def test_banded_full_size_every_row():
     xd = dev(x)
     yd = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
     for mat in (M, C):
-        for cfg in candidates():
+        for cfg in candidates_for(mat):
             print(f"case band {mat.format} {config_name(cfg)}", flush=True)
             yd.fill_(float("nan"))
             mat.set_config(*cfg)
@@ -66,7 +66,7 @@ def test_scrambled_band_reordered_product_every_row():
     bnd = error_bound(Q.nrows, Q.rowptr, Q.colids, Q.vals, x, 1.0, 0.0, None, U64)[perm]
     xd = dev(x[perm])
     yd = torch.empty(Q.nrows, dtype=torch.float64, device="cuda")
-    for cfg in candidates():
+    for cfg in candidates_for(M):
         print(f"case scrambled band {config_name(cfg)}", flush=True)
         yd.fill_(float("nan"))
         M.set_config(*cfg)

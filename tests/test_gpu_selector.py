@@ -17,12 +17,13 @@ from workloads.matrices import batch_matrix, batch_member
 pytestmark = pytest.mark.gpu
 
 K = D.NCLASS
+S0 = D.CLASS_SPMM  # first SpMM class
 
 
 def _mask(F):
     spmm = F[:, 9] > 1.5
     cls = np.arange(K)
-    return np.where(spmm[:, None], cls[None, :] >= 42, cls[None, :] < 42)
+    return np.where(spmm[:, None], cls[None, :] >= S0, cls[None, :] < S0)
 
 
 def _params(seed):
@@ -93,7 +94,7 @@ def test_training_reduces_loss():
     F[:, 9] = 1.0
     best = (F[:, 0] > 0).astype(int) * 3 + (F[:, 1] > 0).astype(int) * 21
     T = np.full((N, K), 2.0, dtype=np.float32)
-    T[:, 42:] = np.inf
+    T[:, S0:] = np.inf
     T[np.arange(N), best] = 1.0
     net = D.Mlp(seed=2)
     losses = net.train(F, T, epochs=40, batch=128, lr=3e-3, tau=0.05, seed=3)
@@ -112,31 +113,34 @@ def test_autotune_sets_fastest_class():
     x = dev(np.ones(A.ncols))
     y = torch.zeros(A.nrows, dtype=torch.float64, device="cuda")
     t = D.autotune(M, 1, x, y, reps=2)
-    assert np.all(np.isfinite(t[:42])) and np.all(np.isinf(t[42:]))
+    assert np.all(np.isfinite(t[:S0])) and np.all(np.isinf(t[S0:]))
     assert S.config_class(M.get_config(), 1) == int(np.argmin(t))
     X = dev(np.ones((A.ncols, 3)))
     Y = torch.zeros(A.nrows, 3, dtype=torch.float64, device="cuda")
     t3 = D.autotune(M, 3, X, Y, reps=2)
-    assert np.all(np.isinf(t3[:42])) and np.all(np.isfinite(t3[42:]))
-    assert S.config_class(M.get_config(), 3) == 42 + int(np.argmin(t3[42:]))
+    assert np.all(np.isinf(t3[:S0])) and np.all(np.isfinite(t3[S0:]))
+    assert S.config_class(M.get_config(), 3) == S0 + int(np.argmin(t3[S0:]))
     M.destroy()
 
 
 def test_class_table_matches_tuning_candidates():
+    assert len(candidates()) == S0
     for k, c in enumerate(candidates()):
         v, l, u, tile, mm = D.class_config(k)
-        assert (v, l) == c[:2] and not mm
-        if v == 0:
-            assert u == c[2]
-        else:
+        assert (v, l, u) == c[:3] and not mm
+        if v == 1:
             assert tile == c[3]
+            assert S.config_class({"variant": v, "lanes": l, "unroll": u, "tile": tile}, 1) == k
+    for k in range(S0, K):
+        v, l, u, tile, mm = D.class_config(k)
+        assert mm and v == 1 and u == 1 and l == 2 ** (k - S0)
 
 
 def test_shipped_selector_beats_the_default_on_unseen_matrices():
     """Matrices from seeds the network was not trained on: the shipped
     network's choice against the library default (no selector) and against
     the exhaustive autotuner.  The autotuner's times are averaged over three
-    collections: the regret divides by the fastest of 49 timings, and with a
+    collections: the regret divides by the fastest of 63 timings, and with a
     single noisy collection that minimum is biased low."""
     torch_or_skip()
     assert os.path.exists(S.WEIGHTS), "trained selector weights are missing"

@@ -8,7 +8,7 @@ import paper_2307_06305_amd as D
 from gpu_util import U32, U64, assert_within, dev, error_bound, host, torch_or_skip
 from oracle import spmv as OS
 from oracle import storage as OST
-from paper_2307_06305_amd.tuning import candidates, config_name
+from paper_2307_06305_amd.tuning import candidates_for, config_name
 from workloads import (config_matrix, laplace_2d_5pt, poisson_3d_7pt, random_banded, random_csr,
                        stencil_3d_27pt, uniform_vector)
 
@@ -71,7 +71,7 @@ def test_spmv_all_configs_match_oracle(A, dtype, fmt):
     for alpha, beta in ((1.0, 0.0), (-0.75, 1.5)):
         ref = OS.spmv_csr(A.nrows, A.ncols, A.rowptr, A.colids, vals, x, alpha, beta, y0)
         bnd = error_bound(A.nrows, A.rowptr, A.colids, vals, x, alpha, beta, y0, u)
-        for cfg in candidates():
+        for cfg in candidates_for(M):
             yd = dev(y0, tdt)
             M.set_config(*cfg)
             M.apply(xd, yd, alpha, beta)
@@ -113,7 +113,7 @@ def test_laplace_2d_closed_forms_bit_exact(fmt):
     expect_ones = on_edge.ravel().astype(np.float64)
     f, idx2 = _grid_quadratic((N, N))
     expect_quad = -4.0 + _ghost_sum((N, N), idx2)
-    for cfg in candidates():
+    for cfg in candidates_for(M):
         M.set_config(*cfg)
         for vec, expect in ((np.ones(N * N), expect_ones), (f, expect_quad)):
             yd = dev(np.zeros(N * N))
@@ -132,7 +132,7 @@ def test_poisson_3d_quadratic_bit_exact(fmt):
          else D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals))
     f, idx = _grid_quadratic(shape)
     expect = -6.0 + _ghost_sum(shape, idx)
-    for cfg in candidates():
+    for cfg in candidates_for(M):
         M.set_config(*cfg)
         yd = dev(np.zeros(A.nrows))
         M.apply(dev(f), yd)
@@ -149,7 +149,7 @@ def test_beta_zero_ignores_nan_and_alpha_zero_scales():
     ref = OS.spmv_csr(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, x)
     bnd = error_bound(A.nrows, A.rowptr, A.colids, A.vals, x, 1.0, 0.0, None, U64)
     y0 = uniform_vector(A.nrows, 2)
-    for cfg in candidates():
+    for cfg in candidates_for(M):
         M.set_config(*cfg)
         yd = dev(np.full(A.nrows, np.nan))
         M.spmv(dev(x), yd, 1.0, 0.0)
@@ -172,7 +172,7 @@ def test_empty_shapes():
         M = D.Matrix.create(nrows, ncols, rp, np.zeros(0, np.int16), np.zeros(0))
         C = D.Matrix.csr_create(nrows, ncols, rp, np.zeros(0, np.int32), np.zeros(0))
         y0 = uniform_vector(nrows, 3)
-        for cfg in candidates():
+        for cfg in candidates_for(M):
             for mat in (M, C):
                 mat.set_config(*cfg)
                 yd = dev(y0)
@@ -180,6 +180,132 @@ def test_empty_shapes():
                 assert np.array_equal(host(yd), 0.5 * y0)
         M.destroy()
         C.destroy()
+
+
+def _runs_matrix(ncols, seed):
+    """Rows of runs of neighbouring columns, for the paired gathers: runs of
+    every length 1..70 starting at column 0, at column 1, ending at the last
+    column and at a random column; rows of short runs with gaps; single
+    entries at the first and last columns; a pair ending at the last
+    column; empty rows.  Columns stay within 32767 of the row (DA16)."""
+    from workloads.matrices import CSR
+    rng = np.random.default_rng(seed)
+    rows = []
+    for L in range(1, min(71, ncols + 1)):
+        for start in {0, min(1, ncols - L), ncols - L, int(rng.integers(0, ncols - L + 1))}:
+            rows.append(np.arange(start, start + L))
+    for _ in range(200):
+        starts = rng.integers(0, max(ncols - 4, 1), int(rng.integers(1, 12)))
+        c = np.concatenate([np.arange(a, a + int(rng.integers(1, 5))) for a in starts])
+        rows.append(np.unique(c[c < ncols]))
+    rows += [np.array([0]), np.array([ncols - 1]), np.array([], dtype=np.int64)]
+    if ncols >= 2:
+        rows.append(np.array([ncols - 2, ncols - 1]))
+    order = rng.permutation(len(rows))
+    rows = [rows[i] for i in order]
+    rl = np.array([r.size for r in rows], dtype=np.int64)
+    rp = np.zeros(len(rows) + 1, dtype=np.int64)
+    np.cumsum(rl, out=rp[1:])
+    cols = np.concatenate(rows).astype(np.int32)
+    return CSR(len(rows), ncols, rp.astype(np.int32), cols, rng.uniform(-1, 1, cols.size),
+               f"runs_{ncols}")
+
+
+@pytest.mark.parametrize("ncols", [600, 2, 1])
+def test_paired_gathers_on_runs_and_edges(ncols):
+    """Paired gathers (stream unroll 2) against the oracle on rows made of
+    runs, including the last column (the load address is clamped there) and
+    matrices with two columns and one column (which take the interleaved
+    kernel), for every lane count and tile, DA16 and CSR32, float64 and
+    float32 (Sec. 4's product)."""
+    torch = torch_or_skip()
+    A = _runs_matrix(ncols, 31 + ncols)
+    e = _encode(A)
+    for f32 in (False, True):
+        vals = A.vals.astype(np.float32) if f32 else A.vals
+        x = uniform_vector(A.ncols, 79)
+        y0 = uniform_vector(A.nrows, 80)
+        if f32:
+            x, y0 = x.astype(np.float32), y0.astype(np.float32)
+        store, tdt, u = (D.F32, torch.float32, U32) if f32 else (D.F64, torch.float64, U64)
+        for fmt in ("da", "csr"):
+            M = (D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], vals, store=store)
+                 if fmt == "da" else
+                 D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, vals, store=store))
+            xd = dev(x, tdt)
+            for alpha, beta in ((1.0, 0.0), (-0.5, 2.0)):
+                ref = OS.spmv_csr(A.nrows, A.ncols, A.rowptr, A.colids, vals, x, alpha, beta, y0)
+                bnd = error_bound(A.nrows, A.rowptr, A.colids, vals, x, alpha, beta, y0, u)
+                for cfg in [c for c in candidates_for(M) if c[0] == D.VAR_STREAM and c[2] == 2]:
+                    M.set_config(*cfg)
+                    yd = dev(y0, tdt)
+                    M.apply(xd, yd, alpha, beta)
+                    assert_within(host(yd), ref, bnd, f"{A.name} {fmt} f32={f32} "
+                                                      f"{config_name(cfg)} alpha={alpha}")
+            M.destroy()
+
+
+def test_paired_gathers_ignore_values_they_do_not_use():
+    """A paired load also brings x[c + 1] (or x[c - 1] at the last column);
+    where that column is not in the row its value is not used: infinities
+    and NaNs there leave y finite and equal to the oracle's product."""
+    torch = torch_or_skip()
+    from workloads.matrices import CSR
+    rng = np.random.default_rng(41)
+    ncols = 401                      # the last column, 400, is even
+    rows = [np.sort(rng.choice(np.arange(0, ncols, 2), size=int(rng.integers(0, 30)),
+                               replace=False)) for _ in range(300)]
+    rows.append(np.array([ncols - 1]))
+    rl = np.array([r.size for r in rows])
+    rp = np.concatenate([[0], np.cumsum(rl)]).astype(np.int32)
+    A = CSR(len(rows), ncols, rp, np.concatenate(rows).astype(np.int32),
+            rng.uniform(-1, 1, int(rp[-1])), "even_columns")
+    x = uniform_vector(ncols, 81)
+    ref = OS.spmv_csr(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, x)
+    bnd = error_bound(A.nrows, A.rowptr, A.colids, A.vals, x, 1.0, 0.0, None, U64)
+    x[1::4] = np.inf                 # odd columns: never in a row
+    x[3::4] = np.nan
+    e = _encode(A)
+    for M in (D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], A.vals),
+              D.Matrix.csr_create(A.nrows, A.ncols, A.rowptr, A.colids, A.vals)):
+        for cfg in [c for c in candidates_for(M) if c[0] == D.VAR_STREAM and c[2] == 2]:
+            M.set_config(*cfg)
+            yd = dev(np.full(A.nrows, np.nan))
+            M.apply(dev(x), yd)
+            assert_within(host(yd), ref, bnd, config_name(cfg))
+        M.destroy()
+
+
+def test_paired_gathers_need_a_plain_stream_cell():
+    """unroll 2 is taken by DA16 and CSR32 stream configurations (with either
+    cache policy; plain loads give the same product); other cells and
+    unroll values are rejected, and the tuner offers paired candidates only
+    where they apply."""
+    torch_or_skip()
+    A = stencil_3d_27pt(6, 3)
+    e = _encode(A)
+    M = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], A.vals)
+    x = dev(uniform_vector(A.ncols, 5))
+    ref = OS.spmv_csr(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, host(x))
+    bnd = error_bound(A.nrows, A.rowptr, A.colids, A.vals, host(x), 1.0, 0.0, None, U64)
+    for cache in (D.CACHE_NT, D.CACHE_PLAIN):
+        M.set_config(D.VAR_STREAM, 4, 2, 2048, cache=cache)
+        assert M.get_config()["unroll"] == 2 and M.takes_paired
+        yd = dev(np.full(A.nrows, np.nan))
+        M.spmv(x, yd)
+        assert_within(host(yd), ref, bnd, f"paired cache={cache}")
+    with pytest.raises(D.DamnError) as err:
+        M.set_config(D.VAR_STREAM, 4, 3, 2048)
+    assert err.value.code == -1  # DAMN_ERR_INVALID_ARG
+    M.destroy()
+    idx, _ = D.encode_index(D.FORMAT_DA8, A.nrows, A.ncols, A.rowptr, A.colids)
+    M8 = D.Matrix.create_format(D.FORMAT_DA8, A.nrows, A.ncols, A.rowptr, idx, A.vals)
+    assert not M8.takes_paired
+    assert all(c[2] == 1 for c in candidates_for(M8) if c[0] == D.VAR_STREAM)
+    with pytest.raises(D.DamnError) as err:
+        M8.set_config(D.VAR_STREAM, 4, 2, 2048)
+    assert err.value.code == -6  # DAMN_ERR_UNSUPPORTED
+    M8.destroy()
 
 
 SPMM_CFGS = ([(D.VAR_VECTOR, lanes, 2048) for lanes in (1, 4, 8, 32, 64)]
@@ -285,7 +411,7 @@ def test_full_size_27pt_every_row():
     bnd = error_bound(A.nrows, A.rowptr, A.colids, A.vals, x, 1.0, 0.0, None, U64)
     yd = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
     for mat in (M, C):
-        for cfg in candidates():
+        for cfg in candidates_for(mat):
             print(f"case 27pt128 {mat.format} {config_name(cfg)}", flush=True)
             yd.fill_(float("nan"))
             mat.set_config(*cfg)

@@ -30,13 +30,17 @@ def _fake_runs(tmp_path, g_da=2, g_csr=2):
 
 
 def test_kernel_names_follow_the_launch():
-    assert P.stream_launch("stream_g4_t1024") == (4, 1024)
+    assert P.stream_launch("stream_g4_t1024") == (4, 1024, 1)
+    assert P.stream_launch("paired_g8_t2048") == (8, 2048, 2)
     assert P.kernel_name("da", "stream_g4_t1024") == \
-        "spmv_stream<short, double, true, 4, false, double, 2>"
+        "spmv_stream<short, double, true, 4, false, double, 2, 1>"
     assert P.kernel_name("csr", "stream_g1_t2048") == \
-        "spmv_stream<int, double, false, 1, false, double, 2>"
-    with pytest.raises(ValueError):
-        P.stream_launch("vector_l4_u2")
+        "spmv_stream<int, double, false, 1, false, double, 2, 1>"
+    assert P.kernel_name("da", "paired_g4_t2048") == \
+        "spmv_stream<short, double, true, 4, false, double, 2, 2>"
+    for bad in ("vector_l4_u2", "pairs_g4_t2048"):
+        with pytest.raises(ValueError):
+            P.stream_launch(bad)
 
 
 def test_summary_scales_by_the_copy_probe(tmp_path):
@@ -104,13 +108,13 @@ def test_source_hash_ignores_comments_only():
 def test_counter_table_keeps_workloads_apart(tmp_path):
     """Means per dispatch by counter, one column per workload and kernel:
     the same kernel symbol in two workloads stays two columns."""
-    k = "void damn::kern::spmv_stream<int, double, false, 4, false, double, 2>(args)"
+    k = "void damn::kern::spmv_stream<int, double, false, 4, false, double, 2, 1>(args)"
     a1, a2, b1 = tmp_path / "a1.csv", tmp_path / "a2.csv", tmp_path / "b1.csv"
     _counters(a1, "TCC_HIT_sum", [(k, 10.0), (k, 20.0), ("other(x)", 5.0)])
     _counters(a2, "TCC_MISS_sum", [(k, 4.0)])
     _counters(b1, "TCC_HIT_sum", [(k, 100.0)])
     m = P.counter_means([str(a1), str(a2)])
-    name = "damn::kern::spmv_stream<int, double, false, 4, false, double, 2>"
+    name = "damn::kern::spmv_stream<int, double, false, 4, false, double, 2, 1>"
     assert m[name] == {"TCC_HIT_sum": 15.0, "TCC_MISS_sum": 4.0}
     out = tmp_path / "c.md"
     P.write_counter_summary([f"wl-a={a1},{a2}", f"wl-b={b1}"], str(out), "t", "cmd", "",

@@ -41,8 +41,8 @@ def test_select_noalloc_matches_select_prob():
             f"n={n}: probabilities differ"
         # without the probability output
         assert np.array_equal(net.select_noalloc(F), want_c)
-        assert set(np.unique(want_c[F[:, 9] > 1.5])) <= set(range(42, D.NCLASS))
-        assert set(np.unique(want_c[F[:, 9] < 1.5])) <= set(range(42))
+        assert set(np.unique(want_c[F[:, 9] > 1.5])) <= set(range(D.CLASS_SPMM, D.NCLASS))
+        assert set(np.unique(want_c[F[:, 9] < 1.5])) <= set(range(D.CLASS_SPMM))
     # nothing to do
     assert net.select_noalloc(np.zeros((0, 16), dtype=np.float32)).size == 0
     # beyond the scratch area: refused with its own status

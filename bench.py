@@ -996,7 +996,7 @@ def main():
                          "default: autotuned")
     ap.add_argument("--profile-da", default="stream_g2_t1024",
                     help="DA-CSR launch shape of the counter run")
-    ap.add_argument("--profile-csr", default="stream_g2_t2048",
+    ap.add_argument("--profile-csr", default="stream_g2_t1024",
                     help="CSR launch shape of the counter run")
     ap.add_argument("--profile-workload", default="27pt",
                     help="matrix of the counter run: 27pt (128^3), band (n 4M, natural order), "

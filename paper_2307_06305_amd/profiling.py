@@ -31,7 +31,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/spmv_kernels.hip", "csrc/spmv_templates.h", "csrc/damn_device.h",
                   "csrc/api.hip")
 DA_LAUNCH = "stream_g2_t1024"   # launch shapes the counter runs use by default
-CSR_LAUNCH = "stream_g2_t2048"
+CSR_LAUNCH = "stream_g2_t1024"
 
 
 def stream_launch(name):

@@ -276,9 +276,10 @@ int damn_bsr_create(damn_mat* out, int32_t format, int32_t nbrows, int32_t nbcol
  *      non-decreasing, in [0, nrows)), idx[nnz] (int16 offsets or int32
  *      columns; every column inside [0, ncols)), vals[nnz] of vals_dtype
  *      stored as store_dtype (float64 or float32).  All checked on the host.
- * Out: *out.  DA-COO takes damn_spmv, COO damn_csr_spmv; a product writes
- *      y <- beta*y first and then adds the rows' sums, each row in one
- *      place, without atomics (the result does not depend on scheduling).
+ * Out: *out.  DA-COO takes damn_spmv, COO damn_csr_spmv; a product is
+ *      one launch that writes every row of y once (rows without entries
+ *      get beta*y), each row summed in one place, without atomics (the
+ *      result does not depend on scheduling).
  * Errors: DAMN_ERR_INVALID_ARG, DAMN_ERR_BAD_CSR (rows out of order or
  *         range, columns out of range), DAMN_ERR_UNSUPPORTED (float16,
  *         nnz >= 2^31), DAMN_ERR_NO_FIT (value overflow), DAMN_ERR_ALLOC,

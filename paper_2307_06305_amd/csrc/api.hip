@@ -138,7 +138,7 @@ void free_mat(damn_mat A) {
   if (A->d_val) hipFree(A->d_val);
   if (A->d_tiles) hipFree(A->d_tiles);
   if (A->d_rows) hipFree(A->d_rows);
-  if (A->d_carry) hipFree(A->d_carry);
+  if (A->d_cross) hipFree(A->d_cross);
   release_cg_work(A);
   hipSetDevice(cur);
   delete A;
@@ -265,7 +265,7 @@ int run_spmv(damn_mat A, const void* x, void* y, double alpha, double beta, void
   if (format_is_coo(A->format)) {
     a.nnz = A->nnz;
     a.coo_rows = A->d_rows;
-    a.coo_carry = static_cast<CooCarry*>(A->d_carry);
+    a.coo_cross = A->d_cross;
     a.nchunks = A->nchunks;
     const hipError_t e = launch_spmv_coo(a);
     return e == hipSuccess ? DAMN_OK : DAMN_ERR_HIP;
@@ -440,10 +440,22 @@ int damn_coo_create(damn_mat* out, int32_t format, int32_t nrows, int32_t ncols,
   if (st != DAMN_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   A->nchunks = (nnz + kCooChunk - 1) / kCooChunk;
+  // per chunk, the end of the row holding its last entry: the chunk where a
+  // row begins sums it to there
+  std::vector<int32_t> cross;
+  try {
+    cross.resize(size_t(A->nchunks > 0 ? A->nchunks : 1), 0);
+  } catch (const std::bad_alloc&) {
+    free_mat(A);
+    return DAMN_ERR_ALLOC;
+  }
+  for (int64_t t = 0; t < A->nchunks; ++t) {
+    const int64_t last = std::min<int64_t>((t + 1) * kCooChunk, nnz) - 1;
+    cross[size_t(t)] = rp[size_t(rows[last]) + 1];
+  }
   const int64_t pe = padded_entries(nnz);
   bool ok = hipMalloc(&A->d_rows, sizeof(int32_t) * pe) == hipSuccess &&
-            hipMalloc(&A->d_carry, sizeof(CooCarry) * size_t(A->nchunks > 0 ? A->nchunks : 1)) ==
-                hipSuccess;
+            hipMalloc(&A->d_cross, sizeof(int32_t) * cross.size()) == hipSuccess;
   if (!ok) {
     free_mat(A);
     return DAMN_ERR_ALLOC;
@@ -451,6 +463,8 @@ int damn_coo_create(damn_mat* out, int32_t format, int32_t nrows, int32_t ncols,
   ok = hipMemsetAsync(A->d_rows, 0, sizeof(int32_t) * pe, s) == hipSuccess &&
        (nnz == 0 || hipMemcpyAsync(A->d_rows, rows, sizeof(int32_t) * nnz,
                                    hipMemcpyHostToDevice, s) == hipSuccess) &&
+       hipMemcpyAsync(A->d_cross, cross.data(), sizeof(int32_t) * cross.size(),
+                      hipMemcpyHostToDevice, s) == hipSuccess &&
        hipStreamSynchronize(s) == hipSuccess;
   if (!ok) {
     free_mat(A);

@@ -25,18 +25,8 @@ struct alignas(8) TileStart {
 // 16-byte copies of a tile's row pointers stay inside the allocation.
 constexpr int32_t kRowptrPad = 16;
 
-// Coordinate formats: entries per workgroup, and what each chunk leaves for
-// the rows cut by its edges (head: the sum of its first segment when that
-// row began in an earlier chunk; through: that row also runs past the chunk;
-// tail, tail_row: the sum and row of its last segment when that row begins in
-// this chunk and runs past it, else tail_row = -1).
+// Coordinate formats: entries per workgroup.
 constexpr int32_t kCooChunk = 1024;
-struct CooCarry {
-  double head;
-  double tail;
-  int32_t tail_row;
-  int32_t through;
-};
 
 struct SpmvArgs {
   int32_t nrows = 0;
@@ -52,10 +42,11 @@ struct SpmvArgs {
   int32_t format = DAMN_FORMAT_DA16;
   int32_t store = DAMN_F64;  // x, y and sums are float64 for DAMN_F64, else float32
   int32_t block = 1;         // block formats: b (rowptr and tiles count block rows)
-  // coordinate formats: entries, their rows, the per-chunk carries
+  // coordinate formats: entries, their rows, per chunk the end of the row
+  // holding its last entry
   int64_t nnz = 0;
   const int32_t* coo_rows = nullptr;
-  CooCarry* coo_carry = nullptr;
+  const int32_t* coo_cross = nullptr;
   int64_t nchunks = 0;
   // stream variant
   int32_t cache = DAMN_CACHE_NT;  // cache policy of the matrix stream (damn_cache)
@@ -74,8 +65,8 @@ hipError_t launch_spmv_grid(const SpmvArgs& a, int variant, int lanes, int unrol
 // Block formats (spmv_bsr.hip): the stream variant over tiles of block rows
 // with `cap` blocks; lanes in {1, 2, 4, 8, 16}; block in {2, 3, 4, 6}.
 hipError_t launch_spmv_bsr(const SpmvArgs& a, int lanes);
-// Coordinate formats (spmv_coo.hip): y <- beta*y, then the chunk and join
-// kernels; entries in row order.
+// Coordinate formats (spmv_coo.hip): one chunk kernel (y <- beta*y alone
+// when alpha == 0 or there are no entries); entries in row order.
 hipError_t launch_spmv_coo(const SpmvArgs& a);
 // Stream variant with the conjugate-gradient epilogue: partial[t] = sum of
 // y_r * w_r over tile t (w = nullptr: w = y), skipped entirely when *done.

@@ -19,7 +19,7 @@ struct damn_mat_s {
   int32_t dtype = DAMN_F64;
   int32_t block = 1;  // b of block formats (rowptr, idx and tiles count block rows)
   int32_t* d_rows = nullptr;  // coordinate formats: row of each entry, padded
-  void* d_carry = nullptr;    // coordinate formats: one CooCarry per chunk
+  int32_t* d_cross = nullptr;  // coordinate formats: per chunk, the end of the row of its last entry
   int64_t nchunks = 0;
   int32_t* d_rowptr = nullptr;
   void* d_idx = nullptr;  // int16 offsets or int32 columns, padded

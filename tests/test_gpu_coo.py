@@ -1,6 +1,7 @@
 """GPU parity of the DA-COO and COO products (diagonal addressing applied to
 one index vector of COO, Sec. 1) against the CPU oracle, through the C ABI:
-rows cut by chunk edges, rows running through several chunks, empty rows,
+rows cut by chunk edges, rows running through several chunks, empty rows
+(also long runs of them before, between and after the rows with entries),
 both scalar types; a closed form bit-exact."""
 
 import numpy as np
@@ -27,10 +28,29 @@ def _runs():
                rng.uniform(-1, 1, int(rp[-1])), "long_runs")
 
 
+def _gaps():
+    # long runs of empty rows before, between and after the rows with
+    # entries (rows without entries get beta*y from the chunk that follows
+    # them, or from the last chunk), rows of 1023..1025 entries next to the
+    # 1024-entry chunk edges
+    rng = np.random.default_rng(4)
+    nrows, ncols = 20000, 30000
+    rl = np.zeros(nrows, dtype=np.int64)
+    rl[3000:3100] = rng.integers(0, 60, 100)
+    rl[9000:9003] = [1023, 1024, 1025]
+    rl[15000:15050] = rng.integers(1, 40, 50)
+    rp = np.concatenate([[0], np.cumsum(rl)])
+    cols = np.concatenate([np.sort(rng.choice(np.arange(max(0, r - 20000), min(ncols, r + 20000)),
+                                              size=int(k), replace=False))
+                           for r, k in enumerate(rl) if k])
+    return CSR(nrows, ncols, rp.astype(np.int32), cols.astype(np.int32),
+               rng.uniform(-1, 1, int(rp[-1])), "empty_gaps")
+
+
 CASES = [laplace_2d_5pt(30), stencil_3d_27pt(12, 4), random_banded(30000, 6, half_band=2000),
          random_csr(900, 600, 7, mean_len=6, empty_frac=0.4, dup_frac=0.2, zero_frac=0.1,
                     shuffle_rows=True),
-         random_csr(300, 800, 8, mean_len=9, band=400), _runs()]
+         random_csr(300, 800, 8, mean_len=9, band=400), _runs(), _gaps()]
 
 pytestmark = pytest.mark.gpu
 

@@ -263,9 +263,11 @@ __global__ __launch_bounds__(256) void spmv_stream(
   double dot = 0.0;
   for (int32_t r = r0 + int32_t(threadIdx.x >> 6) * RPW + (wl % RPW); r < r1; r += 256 / G) {
     const int32_t s = rp_s[r - ar] - a0, e = rp_s[r + 1 - ar] - a0;
-    // the dot epilogue's w_r, loaded with the row's gathers rather than
-    // after its sum
+    // the dot epilogue's w_r and, for beta != 0, y_r: loaded with the row's
+    // gathers rather than after its sum, where they would add a dependent
+    // round trip to the end of the workgroup
     const V wr = (DOT && w && lane == 0) ? w[r] : V(0);
+    const V yo = (read_y && lane == 0) ? y[r] : V(0);
     V sum;
     if constexpr (X == 2)
       sum = row_paired<G>(val_s, idx_s, s, e, lane, x, DA ? r : 0, last);
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(256) void spmv_stream(
       sum = row_interleaved<G>(val_s, idx_s, s, e, lane, DA ? x + r : x);
     if (G > 1) sum = strided_group_sum<G>(sum);
     if (lane == 0) {
-      const V yr = finish(sum, alpha, beta, read_y != 0, y + r);
+      const V yr = read_y ? alpha * sum + beta * yo : alpha * sum;
       // y is written once per product: where a wave's stores fill whole
       // 128-byte lines (float64, at most 4 lanes per row), a non-temporal
       // store keeps y from displacing x in L2.  The conjugate-gradient

@@ -148,6 +148,8 @@ def choose(net, A, M, nrhs, X, Y, threshold=0.2, reps=3):
         t = autotune(M, nrhs, X, Y, reps=reps)
         return int(np.argmin(t)), prob, True
     v, lanes, unroll, tile, _ = class_config(cls)
+    if v == VAR_STREAM and unroll == 2 and not M.takes_paired:
+        unroll = 1  # a cell without paired gathers: the same launch, interleaved
     M.set_config(v, lanes, unroll, tile)
     return cls, prob, False
 

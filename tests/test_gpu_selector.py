@@ -181,6 +181,31 @@ def test_select_probability_matches_oracle_softmax():
     assert np.all((prob > 0) & (prob <= 1.0 + 1e-6))
 
 
+def test_choose_takes_interleaved_gathers_where_paired_do_not_apply():
+    """A network class with paired gathers, chosen for a handle whose cell
+    has none (int8 DA offsets), sets the same lanes and tile with the
+    interleaved gathers."""
+    torch = torch_or_skip()
+    from workloads import stencil_3d_27pt
+    A = stencil_3d_27pt(8, 5)
+    idx, _ = D.encode_index(D.FORMAT_DA8, A.nrows, A.ncols, A.rowptr, A.colids)
+    M8 = D.Matrix.create_format(D.FORMAT_DA8, A.nrows, A.ncols, A.rowptr, idx, A.vals)
+    k = S.config_class({"variant": D.VAR_STREAM, "lanes": 4, "unroll": 2, "tile": 2048}, 1)
+    assert D.class_config(k)[:4] == (D.VAR_STREAM, 4, 2, 2048)
+
+    class Fixed:  # answers class k with probability 1
+        def select(self, f, with_prob=False):
+            return np.array([k]), np.array([1.0], dtype=np.float32)
+
+    x = dev(np.ones(A.ncols))
+    y = torch.zeros(A.nrows, dtype=torch.float64, device="cuda")
+    cls, prob, tuned = S.choose(Fixed(), A, M8, 1, x, y)
+    assert cls == k and not tuned
+    cfg = M8.get_config()
+    assert (cfg["variant"], cfg["lanes"], cfg["unroll"], cfg["tile"]) == (D.VAR_STREAM, 4, 1, 2048)
+    M8.destroy()
+
+
 def test_choose_falls_back_to_the_autotuner():
     """Below the probability threshold the exhaustive autotuner configures
     the handle; above it the network's class is set."""

@@ -140,15 +140,17 @@ __device__ __forceinline__ V row_interleaved(const S* __restrict__ val_s,
 // neighbouring columns (three per stencil line) costs one load per two
 // entries.  cb is the column base (the row for DA offsets, 0 for CSR
 // columns); the load address is clamped to `last` = ncols - 2 (ncols >= 2),
-// so no load reads past x.  Up to four steps are in flight per lane.  The
-// positions read past the chunk (at most e + 1) lie inside the tile's LDS
-// slots, and what they hold is never used.
-template <int G, typename I, typename V, typename S>
+// so no load reads past x.  U steps are in flight per lane: with U = 5 a
+// lane's share of a 27-point row (four or five steps at four lanes per row)
+// issues all its loads before the first wait (U = 4: 101.9 us against
+// 95.3 us for the 27-point 128^3 product).  The positions read past the
+// chunk (at most e + 1) lie inside the tile's LDS slots, and what they hold
+// is never used.
+template <int G, int U, typename I, typename V, typename S>
 __device__ __forceinline__ V row_paired(const S* __restrict__ val_s, const I* __restrict__ idx_s,
                                         int32_t s, int32_t e, int part,
                                         const V* __restrict__ x, int32_t cb, int32_t last) {
   typedef V V2 __attribute__((ext_vector_type(2), aligned(sizeof(V))));
-  constexpr int U = 4;
   const int32_t h = (e - s + G - 1) / G;
   int32_t k = s + part * h;
   const int32_t kend = min(e, k + h);
@@ -269,8 +271,11 @@ __global__ __launch_bounds__(256) void spmv_stream(
     const V wr = (DOT && w && lane == 0) ? w[r] : V(0);
     const V yo = (read_y && lane == 0) ? y[r] : V(0);
     V sum;
+    // five paired steps in flight; four in the conjugate-gradient product
+    // at four or more lanes, where five would take it past 64 VGPRs (and
+    // one wave per SIMD of occupancy)
     if constexpr (X == 2)
-      sum = row_paired<G>(val_s, idx_s, s, e, lane, x, DA ? r : 0, last);
+      sum = row_paired<G, (DOT && G >= 4) ? 4 : 5>(val_s, idx_s, s, e, lane, x, DA ? r : 0, last);
     else
       sum = row_interleaved<G>(val_s, idx_s, s, e, lane, DA ? x + r : x);
     if (G > 1) sum = strided_group_sum<G>(sum);

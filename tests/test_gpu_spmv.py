@@ -308,6 +308,32 @@ def test_paired_gathers_need_a_plain_stream_cell():
     M8.destroy()
 
 
+def test_tuner_sets_its_choice_and_times_every_candidate():
+    """The two-stage tuner: every candidate timed, the choice set on the
+    handle and among the candidates, and the product with it correct."""
+    torch = torch_or_skip()
+    from paper_2307_06305_amd.tuning import autotune
+    A = stencil_3d_27pt(16, 9)
+    e = _encode(A)
+    M = D.Matrix.create(A.nrows, A.ncols, e["rowptr"], e["off"], A.vals)
+    x = uniform_vector(A.ncols, 12)
+    xd = dev(x)
+    yd = torch.zeros(A.nrows, dtype=torch.float64, device="cuda")
+    best, times = autotune(M, xd, yd, reps=3, sustained_s=0.002)
+    assert set(times) == set(candidates_for(M)) and best in times
+    assert all(np.isfinite(t) and t > 0 for t in times.values())
+    cfg = M.get_config()
+    assert (cfg["variant"], cfg["lanes"], cfg["unroll"]) == best[:3]
+    if best[0] == D.VAR_STREAM:
+        assert cfg["tile"] == best[3]
+    ref = OS.spmv_csr(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, x)
+    bnd = error_bound(A.nrows, A.rowptr, A.colids, A.vals, x, 1.0, 0.0, None, U64)
+    yd = dev(np.full(A.nrows, np.nan))
+    M.spmv(xd, yd)
+    assert_within(host(yd), ref, bnd, config_name(best))
+    M.destroy()
+
+
 SPMM_CFGS = ([(D.VAR_VECTOR, lanes, 2048) for lanes in (1, 4, 8, 32, 64)]
              + [(D.VAR_STREAM, lanes, tile) for lanes in (1, 2, 4, 8, 16, 32, 64)
                 for tile in (1024, 4096)])

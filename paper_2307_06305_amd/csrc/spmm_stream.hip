@@ -72,8 +72,12 @@ __global__ __launch_bounds__(256) void spmm_stream(
   __syncthreads();
 
   // 2. G lanes per row, split over the right-hand sides and the entries
-  spmm_tile_rows<I, DA, NRHS, PAIRS>(G, r0, r1, a0, ar, val_s, idx_s, rp_s, X, Y, alpha, beta,
-                                     read_y != 0);
+  if constexpr (SpmmDeep<G, NRHS, PAIRS>::kUse)
+    spmm_tile_rows_deep<I, DA, G, NRHS, PAIRS>(r0, r1, a0, ar, val_s, idx_s, rp_s, X, Y, alpha,
+                                               beta, read_y != 0);
+  else
+    spmm_tile_rows<I, DA, NRHS, PAIRS>(G, r0, r1, a0, ar, val_s, idx_s, rp_s, X, Y, alpha, beta,
+                                       read_y != 0);
 }
 
 }  // namespace kern

@@ -271,11 +271,14 @@ __global__ __launch_bounds__(256) void spmv_stream(
     const V wr = (DOT && w && lane == 0) ? w[r] : V(0);
     const V yo = (read_y && lane == 0) ? y[r] : V(0);
     V sum;
-    // five paired steps in flight; four in the conjugate-gradient product
-    // at four or more lanes, where five would take it past 64 VGPRs (and
-    // one wave per SIMD of occupancy)
+    // five paired steps in flight up to four lanes per row; four at eight or
+    // more lanes, where the shorter parts leave the fifth idle (27-point
+    // rows at eight lanes: 117.2 us with five against 107.7 us with four),
+    // and in the conjugate-gradient product at four or more lanes, where
+    // five would take it past 64 VGPRs (and one wave per SIMD of occupancy)
     if constexpr (X == 2)
-      sum = row_paired<G, (DOT && G >= 4) ? 4 : 5>(val_s, idx_s, s, e, lane, x, DA ? r : 0, last);
+      sum = row_paired<G, (G >= 8 || (DOT && G >= 4)) ? 4 : 5>(val_s, idx_s, s, e, lane, x,
+                                                               DA ? r : 0, last);
     else
       sum = row_interleaved<G>(val_s, idx_s, s, e, lane, DA ? x + r : x);
     if (G > 1) sum = strided_group_sum<G>(sum);

@@ -140,10 +140,9 @@ __device__ __forceinline__ V row_interleaved(const S* __restrict__ val_s,
 // neighbouring columns (three per stencil line) costs one load per two
 // entries.  cb is the column base (the row for DA offsets, 0 for CSR
 // columns); the load address is clamped to `last` = ncols - 2 (ncols >= 2),
-// so no load reads past x.  U steps are in flight per lane: with U = 5 a
-// lane's share of a 27-point row (four or five steps at four lanes per row)
-// issues all its loads before the first wait (U = 4: 101.9 us against
-// 95.3 us for the 27-point 128^3 product).  The positions read past the
+// so no load reads past x.  U steps are in flight per lane, chosen so that
+// a lane's share of a stencil row issues all its loads before the first
+// wait (the kernel picks U by lanes per row).  The positions read past the
 // chunk (at most e + 1) lie inside the tile's LDS slots, and what they hold
 // is never used.
 template <int G, int U, typename I, typename V, typename S>
@@ -271,14 +270,18 @@ __global__ __launch_bounds__(256) void spmv_stream(
     const V wr = (DOT && w && lane == 0) ? w[r] : V(0);
     const V yo = (read_y && lane == 0) ? y[r] : V(0);
     V sum;
-    // five paired steps in flight up to four lanes per row; four at eight or
-    // more lanes, where the shorter parts leave the fifth idle (27-point
-    // rows at eight lanes: 117.2 us with five against 107.7 us with four),
-    // and in the conjugate-gradient product at four or more lanes, where
-    // five would take it past 64 VGPRs (and one wave per SIMD of occupancy)
+    // paired steps in flight: six at one lane per row (a 7-point row with
+    // its one pair takes six steps: 128 x 128 x 1024 box, 1024-entry tiles,
+    // float64 252.9 -> 241.4 us, float32 196.1 -> 181.3 us against five),
+    // five at two and four lanes (27-point rows at four lanes: 95.3 us
+    // against 101.9 us with four); four at eight or more lanes, where the
+    // shorter parts leave a fifth idle (27-point rows at eight lanes:
+    // 117.2 us with five against 107.7 us with four), and in the
+    // conjugate-gradient product at four or more lanes, where five would
+    // take it past 64 VGPRs (and one wave per SIMD of occupancy)
+    constexpr int kPairSteps = G == 1 ? 6 : (G >= 8 || (DOT && G >= 4)) ? 4 : 5;
     if constexpr (X == 2)
-      sum = row_paired<G, (G >= 8 || (DOT && G >= 4)) ? 4 : 5>(val_s, idx_s, s, e, lane, x,
-                                                               DA ? r : 0, last);
+      sum = row_paired<G, kPairSteps>(val_s, idx_s, s, e, lane, x, DA ? r : 0, last);
     else
       sum = row_interleaved<G>(val_s, idx_s, s, e, lane, DA ? x + r : x);
     if (G > 1) sum = strided_group_sum<G>(sum);

@@ -105,26 +105,38 @@ __global__ __launch_bounds__(256) void spmv_bsr_stream(
     const int32_t br = r0 + bro;
     const int32_t s = rp_s[br - ar] - a0, e = rp_s[br + 1 - ar] - a0;
     const V* xs = DA ? x + int64_t(br) * B : x;
-    V acc0 = V(0), acc1 = V(0);
-    int32_t k = s + lane;
-    for (; k + G < e; k += 2 * G) {
-      const V* xa = xs + int64_t(idx_s[k]) * B;
-      const V* xb = xs + int64_t(idx_s[k + G]) * B;
-      const S* va = val_s + (k * B + i) * B;
-      const S* vb = val_s + ((k + G) * B + i) * B;
+    // UB blocks' x values in flight per lane before the first is used (up
+    // to 16 values for b <= 3, 12 for larger blocks, within 64 VGPRs):
+    // 3 x 3 blocks on the 27-point pattern, float64 86.4 -> 81.6 us and
+    // float32 45.3 -> 42.0 us against two blocks
+    constexpr int UB0 = (B <= 3 ? 16 : 12) / B;
+    constexpr int UB = UB0 < 2 ? 2 : (UB0 > 8 ? 8 : UB0);
+    V a2[2] = {V(0), V(0)};
+    for (int32_t k0 = s + lane; k0 < e; k0 += UB * G) {
+      V xv[UB][B];
 #pragma unroll
-      for (int j = 0; j < B; ++j) {
-        acc0 += V(va[j]) * xa[j];
-        acc1 += V(vb[j]) * xb[j];
+      for (int u = 0; u < UB; ++u) {
+        const int32_t k = k0 + u * G;
+        if (k < e) {
+          const V* xa = xs + int64_t(idx_s[k]) * B;
+#pragma unroll
+          for (int j = 0; j < B; ++j) xv[u][j] = xa[j];
+        } else {
+#pragma unroll
+          for (int j = 0; j < B; ++j) xv[u][j] = V(0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int32_t k = k0 + u * G;
+        if (k < e) {
+          const S* va = val_s + (k * B + i) * B;
+#pragma unroll
+          for (int j = 0; j < B; ++j) a2[u & 1] += V(va[j]) * xv[u][j];
+        }
       }
     }
-    if (k < e) {
-      const V* xa = xs + int64_t(idx_s[k]) * B;
-      const S* va = val_s + (k * B + i) * B;
-#pragma unroll
-      for (int j = 0; j < B; ++j) acc0 += V(va[j]) * xa[j];
-    }
-    V sum = acc0 + acc1;
+    V sum = a2[0] + a2[1];
     if (G > 1) sum = strided_group_sum<G>(sum);
     if (lane == 0) {
       V* yr = y + int64_t(br) * B + i;

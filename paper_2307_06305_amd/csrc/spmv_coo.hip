@@ -121,14 +121,25 @@ __global__ __launch_bounds__(256) void coo_chunk(int64_t nnz, int32_t nrows,
     const int32_t prev = sk == 0 ? edge : rows_s[sk - 1];
     for (int32_t g = prev + 1 + gl; g < r; g += G) y[g] = read_y ? beta * y[g] : V(0);
     const V* xs = DA ? x + r : x;
-    V acc = V(0), acc2 = V(0);
-    int32_t k = sk + gl;
-    for (; k + G < ek; k += 2 * G) {
-      acc += val_s[k] * xs[idx_s[k]];
-      acc2 += val_s[k + G] * xs[idx_s[k + G]];
+    // eight x gathers in flight per lane before the first is used: a
+    // 27-point row's share (about seven entries at four lanes) waits once
+    // (27-point 128^3: DA-COO 164.5 -> 154.4 us, COO 186.2 -> 175.0 us
+    // against two in flight; the random band unchanged)
+    V a4[4] = {V(0), V(0), V(0), V(0)};
+    for (int32_t k0 = sk + gl; k0 < ek; k0 += 8 * G) {
+      V v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (k0 + u * G < ek)
+          v[u] = xs[idx_s[k0 + u * G]];
+        else
+          v[u] = V(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k0 + u * G < ek) a4[u & 3] += val_s[k0 + u * G] * v[u];
     }
-    if (k < ek) acc += val_s[k] * xs[idx_s[k]];
-    acc += acc2;
+    V acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
     if (G > 1) acc = strided_group_sum<G>(acc);
     if (gl == 0) {
       if (ek == len + ext && rem > ext)

@@ -352,9 +352,9 @@ int damn_spmm(damn_mat A, const void* X, void* Y, int32_t nrhs, double alpha,
  *                      row and loads x[c], x[c+1] together, using both when
  *                      the next entry's column is c+1 (runs of neighbouring
  *                      columns, as in stencil rows, need half the loads).
- *                      DA16 and CSR32 handles with float64 or float32
- *                      values only (else DAMN_ERR_UNSUPPORTED).  damn_spmv,
- *                      damn_csr_spmv
+ *                      Every scalar cell (DA16, DA8, CSR32, CSR16, any
+ *                      value type); block and coordinate formats return
+ *                      DAMN_ERR_UNSUPPORTED.  damn_spmv, damn_csr_spmv
  *                      and conjugate gradients use it; SpMM and the batch
  *                      take the interleaved gathers with the same lanes.
  */

@@ -382,8 +382,8 @@ class Matrix:
     @property
     def takes_paired(self):
         """Whether the stream variant's paired gathers apply (unroll 2):
-        DA16 and CSR32 handles with float64 or float32 values."""
-        return (self.format in (FORMAT_DA16, FORMAT_CSR32) and self.dtype in (F64, F32)
+        every scalar cell (DA16, DA8, CSR32, CSR16, any value type)."""
+        return (self.format in (FORMAT_DA16, FORMAT_CSR32, FORMAT_DA8, FORMAT_CSR16)
                 and self.block == 1)
 
     def apply(self, x, y, alpha=1.0, beta=0.0, stream=None):

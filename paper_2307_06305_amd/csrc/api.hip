@@ -601,7 +601,7 @@ int damn_set_config(damn_mat A, const damn_config* cfg) {
     if (c.cache == DAMN_CACHE_PLAIN && !plain_cell) return DAMN_ERR_UNSUPPORTED;
     if (c.unroll == 0) c.unroll = 1;
     if (c.unroll != 1 && c.unroll != 2) return DAMN_ERR_INVALID_ARG;
-    if (c.unroll == 2 && !plain_cell) return DAMN_ERR_UNSUPPORTED;
+    if (c.unroll == 2 && (A->block > 1 || format_is_coo(A->format))) return DAMN_ERR_UNSUPPORTED;
     const int st = build_tiles(A, tile_cap(A, c.tile), nullptr);
     if (st != DAMN_OK) return st;
   }

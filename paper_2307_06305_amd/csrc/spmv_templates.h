@@ -366,13 +366,9 @@ template <typename I, typename S, bool DA>
 constexpr bool kHasPlainStream =
     (DA ? sizeof(I) == 2 : sizeof(I) == 4) && (sizeof(S) == 8 || sizeof(S) == 4);
 
-// Paired gathers run where the cell has the plain-stream kernels and the
-// matrix has at least two columns (the host rejects paired configurations
-// of other cells; a one-column matrix takes the interleaved kernel).
-template <typename I, typename S, bool DA>
-bool use_paired(const SpmvArgs& a) {
-  return kHasPlainStream<I, S, DA> && a.gather == 2 && a.ncols >= 2;
-}
+// Paired gathers run in every scalar cell when the matrix has at least two
+// columns (a one-column matrix takes the interleaved kernel).
+inline bool use_paired(const SpmvArgs& a) { return a.gather == 2 && a.ncols >= 2; }
 
 template <typename I, typename S, typename V, bool DA, int G>
 hipError_t stream_g(const SpmvArgs& a) {
@@ -385,7 +381,7 @@ hipError_t stream_g(const SpmvArgs& a) {
   V* y = static_cast<V*>(a.y);
   if constexpr (kHasPlainStream<I, S, DA>) {
     if (a.cache == DAMN_CACHE_PLAIN) {
-      if (use_paired<I, S, DA>(a))
+      if (use_paired(a))
         hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, false, S, 0, 2>), grid, block, lds,
                            a.stream, a.tile_row, a.rowptr, idx, val, x, y, V(a.alpha),
                            V(a.beta), a.read_y, a.cap, a.ncols - 2, nullptr, nullptr, nullptr);
@@ -395,12 +391,12 @@ hipError_t stream_g(const SpmvArgs& a) {
                            V(a.beta), a.read_y, a.cap, 0, nullptr, nullptr, nullptr);
       return hipGetLastError();
     }
-    if (use_paired<I, S, DA>(a)) {
-      hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, false, S, kern::kNonTemporal, 2>), grid,
-                         block, lds, a.stream, a.tile_row, a.rowptr, idx, val, x, y, V(a.alpha),
-                         V(a.beta), a.read_y, a.cap, a.ncols - 2, nullptr, nullptr, nullptr);
-      return hipGetLastError();
-    }
+  }
+  if (use_paired(a)) {
+    hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, false, S, kern::kNonTemporal, 2>), grid,
+                       block, lds, a.stream, a.tile_row, a.rowptr, idx, val, x, y, V(a.alpha),
+                       V(a.beta), a.read_y, a.cap, a.ncols - 2, nullptr, nullptr, nullptr);
+    return hipGetLastError();
   }
   hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, false, S>), grid, block, lds, a.stream,
                      a.tile_row, a.rowptr, idx, val, x, y, V(a.alpha), V(a.beta), a.read_y, a.cap,
@@ -430,7 +426,7 @@ hipError_t stream_dot_g(const SpmvArgs& a, const void* w, double* partial, const
   const V* val = static_cast<const V*>(a.val);
   const V* x = static_cast<const V*>(a.x);
   V* y = static_cast<V*>(a.y);
-  if (use_paired<I, V, DA>(a)) {
+  if (use_paired(a)) {
     hipLaunchKernelGGL((kern::spmv_stream<I, V, DA, G, true, V, kern::kNonTemporal, 2>), grid,
                        block, lds, a.stream, a.tile_row, a.rowptr, idx, val, x, y, V(a.alpha),
                        V(a.beta), a.read_y, a.cap, a.ncols - 2, static_cast<const V*>(w), partial,

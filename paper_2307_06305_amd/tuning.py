@@ -20,7 +20,7 @@ def candidates(paired=True):
     """All (variant, lanes, unroll, tile) the library accepts and the tuner
     tries.  The stream variant's tile is the cap on entries per workgroup and
     its unroll the number of x values per gather load (2: paired gathers,
-    for DA16 and CSR32 handles with float64 or float32 values)."""
+    for the scalar storage cells)."""
     out = [(VECTOR, l, u, 2048) for l in LANES for u in UNROLLS]
     out += [(STREAM, g, x, t) for x in (GATHERS if paired else (1,)) for g in LANES for t in TILES]
     return out

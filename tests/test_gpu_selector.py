@@ -182,14 +182,15 @@ def test_select_probability_matches_oracle_softmax():
 
 
 def test_choose_takes_interleaved_gathers_where_paired_do_not_apply():
-    """A network class with paired gathers, chosen for a handle whose cell
-    has none (int8 DA offsets), sets the same lanes and tile with the
-    interleaved gathers."""
+    """A network class with paired gathers, chosen for a handle whose format
+    has none (DA-BSR), sets the same lanes and tile with the interleaved
+    gathers."""
     torch = torch_or_skip()
-    from workloads import stencil_3d_27pt
-    A = stencil_3d_27pt(8, 5)
-    idx, _ = D.encode_index(D.FORMAT_DA8, A.nrows, A.ncols, A.rowptr, A.colids)
-    M8 = D.Matrix.create_format(D.FORMAT_DA8, A.nrows, A.ncols, A.rowptr, idx, A.vals)
+    from workloads.matrices import block_stencil_27pt
+    A = block_stencil_27pt(6, 2, 5)
+    eb = D.bsr_encode(A.nrows, A.ncols, A.rowptr, A.colids, A.vals, 2, D.FORMAT_DABSR16)
+    MB = D.Matrix.bsr_create(D.FORMAT_DABSR16, A.nrows // 2, A.ncols // 2, 2, eb["browptr"],
+                             eb["bidx"], eb["bvals"])
     k = S.config_class({"variant": D.VAR_STREAM, "lanes": 4, "unroll": 2, "tile": 2048}, 1)
     assert D.class_config(k)[:4] == (D.VAR_STREAM, 4, 2, 2048)
 
@@ -199,11 +200,11 @@ def test_choose_takes_interleaved_gathers_where_paired_do_not_apply():
 
     x = dev(np.ones(A.ncols))
     y = torch.zeros(A.nrows, dtype=torch.float64, device="cuda")
-    cls, prob, tuned = S.choose(Fixed(), A, M8, 1, x, y)
+    cls, prob, tuned = S.choose(Fixed(), A, MB, 1, x, y)
     assert cls == k and not tuned
-    cfg = M8.get_config()
+    cfg = MB.get_config()
     assert (cfg["variant"], cfg["lanes"], cfg["unroll"], cfg["tile"]) == (D.VAR_STREAM, 4, 1, 2048)
-    M8.destroy()
+    MB.destroy()
 
 
 def test_choose_falls_back_to_the_autotuner():

@@ -276,11 +276,11 @@ def test_paired_gathers_ignore_values_they_do_not_use():
         M.destroy()
 
 
-def test_paired_gathers_need_a_plain_stream_cell():
-    """unroll 2 is taken by DA16 and CSR32 stream configurations (with either
-    cache policy; plain loads give the same product); other cells and
-    unroll values are rejected, and the tuner offers paired candidates only
-    where they apply."""
+def test_paired_gathers_need_a_scalar_cell():
+    """unroll 2 is taken by the stream configurations of every scalar cell
+    (with either cache policy where the cell has both) and gives the
+    oracle's product there; block formats and other unroll values are
+    rejected, and the tuner offers paired candidates only where they apply."""
     torch_or_skip()
     A = stencil_3d_27pt(6, 3)
     e = _encode(A)
@@ -298,14 +298,27 @@ def test_paired_gathers_need_a_plain_stream_cell():
         M.set_config(D.VAR_STREAM, 4, 3, 2048)
     assert err.value.code == -1  # DAMN_ERR_INVALID_ARG
     M.destroy()
+    # int8 offsets take paired gathers too
     idx, _ = D.encode_index(D.FORMAT_DA8, A.nrows, A.ncols, A.rowptr, A.colids)
     M8 = D.Matrix.create_format(D.FORMAT_DA8, A.nrows, A.ncols, A.rowptr, idx, A.vals)
-    assert not M8.takes_paired
-    assert all(c[2] == 1 for c in candidates_for(M8) if c[0] == D.VAR_STREAM)
-    with pytest.raises(D.DamnError) as err:
-        M8.set_config(D.VAR_STREAM, 4, 2, 2048)
-    assert err.value.code == -6  # DAMN_ERR_UNSUPPORTED
+    assert M8.takes_paired
+    M8.set_config(D.VAR_STREAM, 2, 2, 1024)
+    yd = dev(np.full(A.nrows, np.nan))
+    M8.spmv(x, yd)
+    assert_within(host(yd), ref, bnd, "paired DA8")
     M8.destroy()
+    # a block format does not
+    from workloads.matrices import block_stencil_27pt
+    B = block_stencil_27pt(4, 2, 3)
+    eb = D.bsr_encode(B.nrows, B.ncols, B.rowptr, B.colids, B.vals, 2, D.FORMAT_DABSR16)
+    MB = D.Matrix.bsr_create(D.FORMAT_DABSR16, B.nrows // 2, B.ncols // 2, 2, eb["browptr"],
+                             eb["bidx"], eb["bvals"])
+    assert not MB.takes_paired
+    assert all(c[2] == 1 for c in candidates_for(MB) if c[0] == D.VAR_STREAM)
+    with pytest.raises(D.DamnError) as err:
+        MB.set_config(D.VAR_STREAM, 4, 2, 2048)
+    assert err.value.code == -6  # DAMN_ERR_UNSUPPORTED
+    MB.destroy()
 
 
 def test_tuner_sets_its_choice_and_times_every_candidate():
